@@ -1,0 +1,250 @@
+"""ctypes front end of the FP64 CPU oracle (``liboracle_rro.so``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg load this module.  The product path (the HIP library and its
+Python binding) never imports it.
+
+All arrays are numpy; FP32 inputs are widened exactly to FP64.  Distances are
+in box units (e.g. Mpc/h); the C code converts to base-grid units.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle_rro.so")
+SOURCES = ["rro_uniform.c", "rro_adjoint.c", "rro_octree.c"]
+
+RAY_OK, RAY_OUT_OF_DOMAIN, RAY_MAX_STEPS = 0, 1, 2
+Q_KAPPA, Q_GAMMA1, Q_GAMMA2 = 0, 1, 2
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", "-std=c11", "-Wall", "-o", LIB + ".tmp"]
+    cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class Segment(C.Structure):
+    _fields_ = [("cell", C.c_int64), ("chi_a", C.c_double), ("chi_b", C.c_double)]
+
+
+SEG_DTYPE = np.dtype([("cell", np.int64), ("chi_a", np.float64), ("chi_b", np.float64)])
+
+
+class _Octree(C.Structure):
+    _fields_ = [("n", C.c_int32), ("max_level", C.c_int32), ("n_octs", C.c_int64),
+                ("child_oct", C.c_void_p), ("oct_parent", C.c_void_p),
+                ("oct_level", C.c_void_p), ("oct_coord", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.rro_centre_tensor_uniform.argtypes = [i32, i32, dbl, vp, vp]
+        L.rro_vertex_tensor_uniform.argtypes = [i32, vp, vp]
+        L.rro_trace_uniform.argtypes = [i32, i32, dbl, vp, i64, vp, vp, vp, vp, dbl, i32, i32,
+                                        vp, vp, i64, i32, vp, vp, vp, vp, vp, i64]
+        L.rro_trace_uniform.restype = i32
+        L.rro_trace_adjoint_uniform.argtypes = [i32, dbl, vp, i64, vp, vp, vp, vp, dbl, vp,
+                                                i32, vp]
+        L.rro_trace_adjoint_uniform.restype = i32
+        L.rro_octree_check.argtypes = [vp]
+        L.rro_octree_check.restype = i32
+        L.rro_centre_tensor_octree.argtypes = [vp, vp, vp]
+        L.rro_corner_tensor_octree.argtypes = [vp, vp, vp]
+        L.rro_vertex_weights.argtypes = [i32, i32, i32, vp, vp, vp]
+        L.rro_trace_octree.argtypes = [vp, dbl, vp, i64, vp, vp, vp, vp, dbl, vp, vp, i64, i32,
+                                       vp, vp, vp, vp, vp, i64]
+        L.rro_trace_octree.restype = i32
+        L.rro_cell_integral.argtypes = [vp, vp, dbl, vp, vp, dbl, dbl, dbl]
+        L.rro_cell_integral.restype = dbl
+        L.rro_projection.argtypes = [vp, vp, i32]
+        L.rro_projection.restype = dbl
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------- uniform --
+def centre_tensor(phi, open_boundary=False, h=1.0):
+    """Eq. (tidalexample) at every cell centre; returns (n^3, 6)."""
+    phi = _f64(phi)
+    n = phi.shape[0]
+    tc = np.empty((n ** 3, 6))
+    lib().rro_centre_tensor_uniform(n, int(open_boundary), h, _p(phi), _p(tc))
+    return tc
+
+
+def vertex_tensor(phi, open_boundary=False):
+    """Centre tensor averaged to vertices (grid units, h = 1); returns (n^3, 6)."""
+    phi = _f64(phi)
+    n = phi.shape[0]
+    tc = centre_tensor(phi, open_boundary)
+    tv = np.empty_like(tc)
+    lib().rro_vertex_tensor_uniform(n, _p(tc), _p(tv))
+    return tv
+
+
+def _per_ray(v, n):
+    v = np.asarray(v, dtype=np.float64)
+    if v.ndim == 0:
+        v = np.full(n, float(v))
+    return np.ascontiguousarray(v)
+
+
+@dataclass
+class TraceResult:
+    kappa: np.ndarray
+    hash: np.ndarray
+    ncross: np.ndarray
+    status: np.ndarray
+    log: np.ndarray | None = None
+
+
+def trace_uniform(n, box, observer, dirs, chi_s, chi_hi, chi_lo, *, tv=None, tc=None,
+                  phi=None, open_boundary=False, kappa_scale=1.0, quantity=Q_KAPPA,
+                  ngp=False, max_steps=1 << 40, threads=0, log_stride=0) -> TraceResult:
+    """Trace rays (FP64).  Give ``tv`` (vertex tensor) / ``tc`` (centre tensor,
+    for NGP) or ``phi`` to have them computed here."""
+    dirs = _f64(dirs).reshape(-1, 3)
+    nr = dirs.shape[0]
+    if phi is not None:
+        if ngp:
+            tc = centre_tensor(phi, open_boundary)
+        else:
+            tv = vertex_tensor(phi, open_boundary)
+    obs = _f64(observer)
+    cs, ch, cl = _per_ray(chi_s, nr), _per_ray(chi_hi, nr), _per_ray(chi_lo, nr)
+    kappa = np.zeros(nr)
+    hsh = np.zeros(nr, dtype=np.uint64)
+    ncr = np.zeros(nr, dtype=np.int64)
+    st = np.zeros(nr, dtype=np.int32)
+    log = np.zeros((nr, log_stride), dtype=SEG_DTYPE) if log_stride else None
+    tv_ = _f64(tv) if tv is not None else None
+    tc_ = _f64(tc) if tc is not None else None
+    lib().rro_trace_uniform(n, int(open_boundary), float(box), _p(obs), nr, _p(dirs), _p(cs),
+                            _p(ch), _p(cl), float(kappa_scale), quantity, int(ngp), _p(tv_),
+                            _p(tc_), int(max_steps), int(threads), _p(kappa), _p(hsh),
+                            _p(ncr), _p(st), _p(log), int(log_stride))
+    return TraceResult(kappa, hsh, ncr, st, log)
+
+
+def trace_adjoint_uniform(n, box, observer, dirs, chi_s, chi_hi, chi_lo, dl_dkappa,
+                          kappa_scale=1.0, threads=0):
+    dirs = _f64(dirs).reshape(-1, 3)
+    nr = dirs.shape[0]
+    out = np.zeros(n ** 3)
+    w = _f64(dl_dkappa)
+    lib().rro_trace_adjoint_uniform(n, float(box), _p(_f64(observer)), nr, _p(dirs),
+                                    _p(_per_ray(chi_s, nr)), _p(_per_ray(chi_hi, nr)),
+                                    _p(_per_ray(chi_lo, nr)), float(kappa_scale), _p(w),
+                                    int(threads), _p(out))
+    return out.reshape(n, n, n)
+
+
+def cell_integral(Q, p1, h, direction, o, chis, chi_a, chi_b):
+    """Eq. (Iclensing) for one cell (grid units)."""
+    return lib().rro_cell_integral(_p(_f64(Q)), _p(_f64(p1)), float(h), _p(_f64(direction)),
+                                   _p(_f64(o)), float(chis), float(chi_a), float(chi_b))
+
+
+def projection(direction, T, quantity=Q_KAPPA):
+    """Integrand projection of a tensor T = (xx, yy, zz, xy, xz, yz)."""
+    return lib().rro_projection(_p(_f64(direction)), _p(_f64(T)), int(quantity))
+
+
+# ---------------------------------------------------------------------- octree --
+class Octree:
+    """Host octree: base n^3 cells, then 8 cells per oct in BFS order."""
+
+    def __init__(self, n, child_oct, oct_parent, oct_level, oct_coord, max_level):
+        self.n = int(n)
+        self.child_oct = np.ascontiguousarray(child_oct, dtype=np.int32)
+        self.oct_parent = np.ascontiguousarray(oct_parent, dtype=np.int64)
+        self.oct_level = np.ascontiguousarray(oct_level, dtype=np.int32)
+        self.oct_coord = np.ascontiguousarray(oct_coord, dtype=np.int32).reshape(-1, 3)
+        self.max_level = int(max_level)
+        self.n_octs = int(self.oct_level.shape[0])
+        self._c = _Octree(self.n, self.max_level, self.n_octs, _p(self.child_oct),
+                          _p(self.oct_parent), _p(self.oct_level), _p(self.oct_coord))
+
+    @property
+    def n_cells(self):
+        return self.n ** 3 + 8 * self.n_octs
+
+    def ref(self):
+        return C.byref(self._c)
+
+
+def octree_check(t: Octree) -> int:
+    return int(lib().rro_octree_check(t.ref()))
+
+
+def centre_tensor_octree(t: Octree, phi):
+    phi = _f64(phi)
+    assert phi.shape[0] == t.n_cells
+    tc = np.empty((t.n_cells, 6))
+    lib().rro_centre_tensor_octree(t.ref(), _p(phi), _p(tc))
+    return tc
+
+
+def corner_tensor_octree(t: Octree, tc):
+    cv = np.empty((t.n_cells, 8, 6))
+    lib().rro_corner_tensor_octree(t.ref(), _p(_f64(tc)), _p(cv))
+    return cv
+
+
+def vertex_weights(dim, n_coarse, n_fv):
+    n_fv = np.ascontiguousarray(n_fv, dtype=np.int32)
+    ac = C.c_double()
+    af = np.zeros(len(n_fv))
+    lib().rro_vertex_weights(dim, n_coarse, len(n_fv), _p(n_fv), C.byref(ac), _p(af))
+    return ac.value, af
+
+
+def trace_octree(t: Octree, box, observer, dirs, chi_s, chi_hi, chi_lo, *, cv=None, tc=None,
+                 phi=None, kappa_scale=1.0, max_steps=1 << 40, threads=0,
+                 log_stride=0) -> TraceResult:
+    dirs = _f64(dirs).reshape(-1, 3)
+    nr = dirs.shape[0]
+    if cv is None and tc is None:
+        tc = centre_tensor_octree(t, phi)
+    kappa = np.zeros(nr)
+    hsh = np.zeros(nr, dtype=np.uint64)
+    ncr = np.zeros(nr, dtype=np.int64)
+    st = np.zeros(nr, dtype=np.int32)
+    log = np.zeros((nr, log_stride), dtype=SEG_DTYPE) if log_stride else None
+    cv_ = _f64(cv) if cv is not None else None
+    tc_ = _f64(tc) if tc is not None else None
+    lib().rro_trace_octree(t.ref(), float(box), _p(_f64(observer)), nr, _p(dirs),
+                           _p(_per_ray(chi_s, nr)), _p(_per_ray(chi_hi, nr)),
+                           _p(_per_ray(chi_lo, nr)), float(kappa_scale), _p(cv_), _p(tc_),
+                           int(max_steps), int(threads), _p(kappa), _p(hsh), _p(ncr), _p(st),
+                           _p(log), int(log_stride))
+    return TraceResult(kappa, hsh, ncr, st, log)

@@ -1,0 +1,423 @@
+"""Seeded synthetic inputs for the Method-B convergence path.
+
+This module produces *inputs only*: cosmological distances, ray directions,
+potential fields and AMR octrees.  It holds none of the ray-tracing
+arithmetic (no tidal tensor, no vertex interpolation, no cell walk, no
+per-cell integral), so both the HIP path and the FP64 oracle can consume its
+arrays without sharing any of the method's code.
+
+Paper references (RAY-RAMSES, arXiv:1601.02012):
+  * ray angular grid: Sec. III C, Eq. (txty); ray ids: Eq. (rayid);
+  * comoving distance chi(z) = c int dz/H(z): Sec. III B, below Eq. (raypos);
+  * cosmology of the lensing runs (Omega_b, Omega_c, h): Sec. VI A;
+  * Gaussian test potential: Sec. V, Eq. (gaussian);
+  * Poisson relation used for delta -> Phi: Sec. IV D, Eq. (kappa2).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# ---------------------------------------------------------------- cosmology --
+C_OVER_H0 = 2997.92458          # c/H0 in Mpc/h
+OMEGA_M = 0.049 + 0.267         # Sec. VI A: Omega_b0 + Omega_c0
+OMEGA_L = 1.0 - OMEGA_M
+
+
+def _E(z):
+    return math.sqrt(OMEGA_M * (1.0 + z) ** 3 + OMEGA_L)
+
+
+def _gl_nodes(n=64):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return x, w
+
+
+def _integrate(f, a, b, pieces=64, order=32):
+    """Composite Gauss-Legendre quadrature in FP64 (smooth integrands)."""
+    x, w = _gl_nodes(order)
+    edges = np.linspace(a, b, pieces + 1)
+    tot = 0.0
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        mid, half = 0.5 * (lo + hi), 0.5 * (hi - lo)
+        tot += half * sum(wi * f(mid + half * xi) for xi, wi in zip(x, w))
+    return tot
+
+
+def chi_of_z(z: float) -> float:
+    """Comoving distance in Mpc/h for flat LCDM with Omega_m = 0.316."""
+    if z <= 0.0:
+        return 0.0
+    return C_OVER_H0 * _integrate(lambda t: 1.0 / _E(t), 0.0, float(z), pieces=16, order=24)
+
+
+def z_of_chi(chi: float) -> float:
+    """Inverse of chi_of_z by bisection (FP64)."""
+    lo, hi = 0.0, 20.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if chi_of_z(mid) < chi:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo < 1e-15:
+            break
+    return 0.5 * (lo + hi)
+
+
+def growth_D(a: float) -> float:
+    """Linear growth D+(a) of flat LCDM (unnormalised integral form)."""
+    if a <= 0.0:
+        return 0.0
+    H = lambda aa: math.sqrt(OMEGA_M / aa ** 3 + OMEGA_L)
+    integral = _integrate(lambda aa: 1.0 / (aa * H(aa)) ** 3, 1e-8, a, pieces=32, order=24)
+    return 2.5 * OMEGA_M * H(a) * integral
+
+
+# --------------------------------------------------------------- directions --
+def fov_angles(fov: float, n: int) -> np.ndarray:
+    """Eq. (txty): theta_i = fov/(n-1) * (i-1) - fov/2, i = 1..n (radians).
+
+    A single ray (n == 1) sits on the bundle axis."""
+    if n == 1:
+        return np.zeros(1)
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return fov / (n - 1) * (i - 1.0) - fov / 2.0
+
+
+def _basis(center):
+    e3 = np.asarray(center, dtype=np.float64)
+    e3 = e3 / math.sqrt(float(e3 @ e3))
+    helper = np.array([0.0, 0.0, 1.0]) if abs(e3[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
+    if abs(e3[0]) < 1e-300 and abs(e3[1]) < 1e-300:
+        e1, e2 = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+        if e3[2] < 0:
+            e2 = -e2
+        return e1, e2, e3
+    e1 = np.cross(helper, e3)
+    e1 /= math.sqrt(float(e1 @ e1))
+    e2 = np.cross(e3, e1)
+    return e1, e2, e3
+
+
+def fov_directions(center, fov_x: float, fov_y: float, nx: int, ny: int) -> np.ndarray:
+    """Unit ray directions (observer -> source), shape (ny*nx, 3), FP64.
+
+    Flat-sky gnomonic mapping of the Eq. (txty) angles about ``center``;
+    row-major by ray id, ray id = iy*nx + ix (0-based Eq. (rayid))."""
+    tx = np.tan(fov_angles(fov_x, nx))
+    ty = np.tan(fov_angles(fov_y, ny))
+    e1, e2, e3 = _basis(center)
+    d = (tx[None, :, None] * e1[None, None, :] + ty[:, None, None] * e2[None, None, :]
+         + e3[None, None, :])
+    d = d.reshape(-1, 3)
+    norm = np.sqrt(np.sum(d * d, axis=1))
+    return np.ascontiguousarray(d / norm[:, None])
+
+
+def rayid(ix, iy, nx):
+    """0-based Eq. (rayid)."""
+    return iy * nx + ix
+
+
+def rayid_inverse(rid, nx):
+    return rid % nx, rid // nx
+
+
+# ------------------------------------------------------------------- fields --
+def _kgrid(n: int, box: float):
+    k1 = 2.0 * np.pi * np.fft.fftfreq(n, d=box / n)
+    kz = 2.0 * np.pi * np.fft.rfftfreq(n, d=box / n)
+    return k1, kz
+
+
+def _k2(n, box):
+    k1, kz = _kgrid(n, box)
+    return (k1[:, None, None] ** 2 + k1[None, :, None] ** 2 + kz[None, None, :] ** 2)
+
+
+def gaussian_field(n: int, box: float, rng: np.random.Generator, slope: float = -2.0,
+                   workers: int = -1) -> np.ndarray:
+    """Zero-mean, unit-variance Gaussian field with P(k) ~ k^slope, [z][y][x]."""
+    import scipy.fft as sfft
+    w = rng.standard_normal((n, n, n))
+    wk = sfft.rfftn(w, workers=workers)
+    del w
+    k2 = _k2(n, box)
+    k2[0, 0, 0] = 1.0
+    wk *= k2 ** (slope / 4.0)
+    wk[0, 0, 0] = 0.0
+    del k2
+    g = sfft.irfftn(wk, s=(n, n, n), workers=workers)
+    g -= g.mean()
+    g /= g.std()
+    return g
+
+
+def lognormal_delta(n: int, box: float, rng: np.random.Generator, slope: float = -2.0,
+                    sigma_g: float = 1.0) -> np.ndarray:
+    g = gaussian_field(n, box, rng, slope) * sigma_g
+    return np.exp(g - 0.5 * sigma_g ** 2) - 1.0
+
+
+def poisson_phi(delta: np.ndarray, box: float, a: float = 1.0, workers: int = -1) -> np.ndarray:
+    """Phi/c^2 from delta with the comoving Poisson relation (continuum k^2).
+
+    nabla^2 (Phi/c^2) = (3/2) Omega_m (H0/c)^2 delta / a, as used in Eq. (kappa2)."""
+    import scipy.fft as sfft
+    n = delta.shape[0]
+    dk = sfft.rfftn(delta, workers=workers)
+    k2 = _k2(n, box)
+    k2[0, 0, 0] = 1.0
+    dk *= -1.5 * OMEGA_M / (C_OVER_H0 ** 2 * a) / k2
+    dk[0, 0, 0] = 0.0
+    return sfft.irfftn(dk, s=delta.shape, workers=workers)
+
+
+def gaussian_potential(n: int, box: float, amp: float, sigma: float, center=None,
+                       pad: int = 0) -> np.ndarray:
+    """Eq. (gaussian) sampled at cell centres of an n^3 grid of side ``box``.
+
+    With ``pad`` > 0 the grid is extended by ``pad`` ghost cells per side
+    (same cell size); returns shape (n+2pad)^3 in [z][y][x] order."""
+    h = box / n
+    if center is None:
+        center = (0.5 * box,) * 3
+    idx = (np.arange(-pad, n + pad, dtype=np.float64) + 0.5) * h
+    z = idx[:, None, None] - center[2]
+    y = idx[None, :, None] - center[1]
+    x = idx[None, None, :] - center[0]
+    r2 = x * x + y * y + z * z
+    return amp * np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+# ------------------------------------------------------------ configurations --
+@dataclass
+class Bundle:
+    dirs: np.ndarray            # (n_rays, 3) FP64 unit vectors
+    nx: int
+    ny: int
+    chi_s: float
+    chi_hi: float
+    chi_lo: float
+    center: tuple = (0.0, 0.0, 1.0)
+    fov_x: float = 0.0
+    fov_y: float = 0.0
+
+
+@dataclass
+class UniformCase:
+    name: str
+    n: int
+    box: float
+    phi: np.ndarray             # [z][y][x]
+    observer: tuple
+    bundles: list
+    segments: list = field(default_factory=list)   # list of (chi_hi, chi_lo, scale)
+    open_boundary: bool = False
+
+
+def seeds(config: int, n_streams: int = 4):
+    ss = np.random.SeedSequence(1000 + config)
+    return [np.random.default_rng(s) for s in ss.spawn(n_streams)]
+
+
+def config1(n: int = 64, box: float = 256.0, nray: int = 128) -> UniformCase:
+    """Plain FP64 case: 64^3 Gaussian delta with P ~ k^-2, box 256 Mpc/h,
+    observer at the box corner, 128^2 rays over 2x2 deg, chi_s = 256 Mpc/h."""
+    rf, *_ = seeds(1)
+    delta = gaussian_field(n, box, rf, slope=-2.0)
+    phi = poisson_phi(delta, box)
+    fov = math.radians(2.0)
+    d = fov_directions((0.0, 0.0, 1.0), fov, fov, nray, nray)
+    b = Bundle(d, nray, nray, 256.0, 256.0, 0.0, (0.0, 0.0, 1.0), fov, fov)
+    return UniformCase("c1", n, box, phi, (0.0, 0.0, 0.0), [b])
+
+
+def lightcone_segments(n_seg: int = 20, a_src: float = 0.5):
+    """Equal steps in the scale factor from a_src to 1: (chi_hi, chi_lo, s_k).
+
+    s_k = [D(a)/a]/[D(1)/1] at the segment mid-point scales the potential of
+    synthetic N-body step k (the potential is static within a step)."""
+    a = np.linspace(a_src, 1.0, n_seg + 1)
+    chis = [chi_of_z(1.0 / ai - 1.0) for ai in a]
+    d1 = growth_D(1.0)
+    out = []
+    for k in range(n_seg):
+        am = 0.5 * (a[k] + a[k + 1])
+        out.append((chis[k], chis[k + 1], (growth_D(am) / am) / d1))
+    return out
+
+
+def config2_phi0(n: int = 512, box: float = 1000.0) -> np.ndarray:
+    rf, *_ = seeds(2)
+    delta = lognormal_delta(n, box, rf, slope=-2.0, sigma_g=1.0)
+    return poisson_phi(delta, box)
+
+
+def config2(n: int = 512, box: float = 1000.0, nray: int = 2048, fov_deg: float = 5.0,
+            n_seg: int = 20) -> UniformCase:
+    """Light cone to z = 1 through a replicated 512^3 box of 1 Gpc/h,
+    2048^2 rays over 5x5 deg, 20 chi-segments (one per synthetic step)."""
+    phi0 = config2_phi0(n, box)
+    chi_s = chi_of_z(1.0)
+    fov = math.radians(fov_deg)
+    d = fov_directions((0.0, 0.0, 1.0), fov, fov, nray, nray)
+    b = Bundle(d, nray, nray, chi_s, chi_s, 0.0, (0.0, 0.0, 1.0), fov, fov)
+    segs = lightcone_segments(n_seg)
+    return UniformCase("c2", n, box, phi0, (0.0, 0.0, 0.0), [b], segs)
+
+
+def config5(n: int = 256, box: float = 256.0, nray: int = 1024, fov_deg: float = 5.0):
+    """Adjoint case: 256^3 FP32 Gaussian potential, 1024^2 rays over 5x5 deg,
+    chi_s = 256, plus seeded loss weights w ~ N(0,1)."""
+    rf, rw, *_ = seeds(5)
+    delta = gaussian_field(n, box, rf, slope=-2.0)
+    phi = poisson_phi(delta, box).astype(np.float32)
+    fov = math.radians(fov_deg)
+    d = fov_directions((0.0, 0.0, 1.0), fov, fov, nray, nray)
+    b = Bundle(d, nray, nray, 256.0, 256.0, 0.0, (0.0, 0.0, 1.0), fov, fov)
+    w = rw.standard_normal(nray * nray)
+    return UniformCase("c5", n, box, phi, (0.0, 0.0, 0.0), [b]), w
+
+
+# ------------------------------------------------------------------- octrees --
+@dataclass
+class OctreeInput:
+    """Octree in the library layout: base cells 0..n^3-1 ([z][y][x]); oct k owns
+    cells n^3 + 8k + (ix + 2iy + 4iz); octs in breadth-first order."""
+    n: int
+    max_level: int
+    child_oct: np.ndarray       # int32 [n_cells]
+    oct_parent: np.ndarray      # int64 [n_octs]
+    oct_level: np.ndarray       # int32 [n_octs]
+    oct_coord: np.ndarray       # int32 [n_octs, 3] level coords of child 0
+    cell_level: np.ndarray      # int32 [n_cells]
+    cell_coord: np.ndarray      # int64 [n_cells, 3] level coords
+
+    @property
+    def n_cells(self):
+        return self.child_oct.shape[0]
+
+    @property
+    def n_octs(self):
+        return self.oct_level.shape[0]
+
+    def centres(self, box):
+        """Cell-centre positions in box units, (n_cells, 3) as (x, y, z)."""
+        h = (box / self.n) / (2.0 ** self.cell_level)
+        return (self.cell_coord + 0.5) * h[:, None]
+
+    def leaves(self):
+        return np.nonzero(self.child_oct < 0)[0]
+
+
+def _key(c, nl):
+    c = np.mod(c, nl)
+    return (c[..., 2] * nl + c[..., 1]) * nl + c[..., 0]
+
+
+def _unkey(k, nl):
+    return np.stack([k % nl, (k // nl) % nl, k // (nl * nl)], axis=-1)
+
+
+_OFF27 = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)],
+                  dtype=np.int64)
+_CHILD = np.array([(c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)], dtype=np.int64)
+
+
+def build_octree(n: int, max_level: int, refine) -> OctreeInput:
+    """Build a 2:1-balanced (faces, edges and corners) periodic octree.
+
+    ``refine(level, coords)`` gets the level-l integer coords (m, 3) of existing
+    cells and returns a boolean mask of those to refine (l < max_level)."""
+    refined = []                                  # sorted keys per level
+    exist = np.arange(n ** 3, dtype=np.int64)     # existing cell keys at level 0
+    for l in range(max_level):
+        nl = n << l
+        mask = np.asarray(refine(l, _unkey(exist, nl)), dtype=bool)
+        refined.append(np.unique(exist[mask]))
+        kids = (2 * _unkey(refined[l], nl)[:, None, :] + _CHILD[None]).reshape(-1, 3)
+        exist = np.unique(_key(kids, nl * 2))
+    # 2:1 balance: a refined level-l cell needs its 26 neighbours (and itself)
+    # to exist at level l, i.e. their parents refined at level l-1.
+    for l in range(max_level - 1, 0, -1):
+        if refined[l].size == 0:
+            continue
+        nl = n << l
+        c = _unkey(refined[l], nl)
+        nb = (c[:, None, :] + _OFF27[None]).reshape(-1, 3)
+        parents = np.unique(_key(np.floor_divide(np.mod(nb, nl), 2), nl // 2))
+        refined[l - 1] = np.union1d(refined[l - 1], parents)
+    # the union may have created refined cells whose parent is not refined:
+    # close upwards (a cell exists only if its parent is refined)
+    for l in range(1, max_level):
+        nl = n << l
+        par = np.unique(_key(np.floor_divide(_unkey(refined[l], nl), 2), nl // 2))
+        missing = np.setdiff1d(par, refined[l - 1])
+        if missing.size:
+            raise RuntimeError("balance closure failed")
+    # breadth-first layout
+    n_base = n ** 3
+    cell_level = [np.zeros(n_base, np.int32)]
+    cell_coord = [_unkey(np.arange(n_base, dtype=np.int64), n)]
+    oct_parent, oct_level, oct_coord = [], [], []
+    # cell index of each existing cell per level, as sorted (key, index) arrays
+    lvl_keys = np.arange(n_base, dtype=np.int64)
+    lvl_index = np.arange(n_base, dtype=np.int64)
+    next_cell = n_base
+    n_oct = 0
+    child_oct_parts = []
+    for l in range(max_level):
+        nl = n << l
+        r = refined[l]
+        pos = np.searchsorted(lvl_keys, r)
+        assert np.all(lvl_keys[pos] == r)
+        pidx = lvl_index[pos]
+        order = np.argsort(pidx)                  # BFS: parents in cell order
+        pidx = pidx[order]
+        pc = _unkey(r[order], nl)
+        k = np.arange(n_oct, n_oct + pidx.size, dtype=np.int64)
+        child_oct_parts.append((pidx, k))
+        oct_parent.append(pidx)
+        oct_level.append(np.full(pidx.size, l + 1, np.int32))
+        oct_coord.append(2 * pc)
+        kids = (2 * pc[:, None, :] + _CHILD[None]).reshape(-1, 3)
+        kid_index = next_cell + np.arange(kids.shape[0], dtype=np.int64)
+        cell_level.append(np.full(kids.shape[0], l + 1, np.int32))
+        cell_coord.append(kids)
+        kk = _key(kids, 2 * nl)
+        srt = np.argsort(kk)
+        lvl_keys, lvl_index = kk[srt], kid_index[srt]
+        next_cell += kids.shape[0]
+        n_oct += pidx.size
+    child_oct = np.full(next_cell, -1, np.int32)
+    for pidx, k in child_oct_parts:
+        child_oct[pidx] = k.astype(np.int32)
+    cat = lambda xs, dt, shape: (np.concatenate(xs).astype(dt) if xs else np.zeros(shape, dt))
+    return OctreeInput(n, max_level, child_oct,
+                       cat(oct_parent, np.int64, (0,)), cat(oct_level, np.int32, (0,)),
+                       cat(oct_coord, np.int32, (0, 3)).reshape(-1, 3),
+                       np.concatenate(cell_level).astype(np.int32),
+                       np.concatenate(cell_coord).astype(np.int64))
+
+
+def random_octree(n: int, max_level: int, p: float, rng: np.random.Generator,
+                  region=None) -> OctreeInput:
+    """Octree refined at random (probability p per cell and level), optionally
+    only inside ``region`` = (lo, hi) in base-cell units."""
+    def refine(l, c):
+        m = rng.random(c.shape[0]) < p
+        if region is not None:
+            lo, hi = region
+            x = (c + 0.5) / float(1 << l)
+            m &= np.all((x >= lo) & (x < hi), axis=1)
+        return m
+    return build_octree(n, max_level, refine)
+
+
+def full_octree(n: int, level: int) -> OctreeInput:
+    """Every cell refined down to ``level`` (equivalent to a uniform n*2^level grid)."""
+    return build_octree(n, level, lambda l, c: np.ones(c.shape[0], bool))
