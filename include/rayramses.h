@@ -1,0 +1,230 @@
+/*
+ * rayramses.h -- C ABI of the MI355X (gfx950) Method-B weak-lensing ray tracer.
+ *
+ * The library integrates, along straight rays from a source at comoving
+ * distance chi_s to an observer, the convergence
+ *     kappa = int g(chi_s, chi) [tr T - n^T T n] dchi,  g = chi (chi_s - chi) / chi_s,
+ * where T = d_a d_b Phi is the tidal tensor of the potential (RAY-RAMSES,
+ * arXiv:1601.02012, Sec. IV A Eq. (kappa), Sec. IV B Eqs. (Iclensing),
+ * (n1n1), (n2n2), Sec. IV C Eq. (tidalexample)).  The integral is split into
+ * one piece per crossed cell (Eqs. (sumIc), (Ic)); inside a cell the integrand
+ * is the trilinear reconstruction from the cell's eight vertex values
+ * (Eq. trilinear_int), and the vertex values are interpolated from cell
+ * centres (Sec. III F; Eqs. (alphac3d), (alphaf3d) at refinement boundaries).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named "device" are HIP device pointers owned by the caller; the
+ *    library never frees them.  "host" pointers are read before the call
+ *    returns.  Opaque handles (rr_tensor, rr_plan) are owned by the library and
+ *    released by their destroy call.
+ *  - Calls taking a stream are asynchronous on it (NULL = the default stream)
+ *    and allocate nothing once the plan has seen the bundle set (see
+ *    rr_trace_rays).  Argument errors are detected on the host before any
+ *    launch: the call returns a negative rr_status and rr_last_error() gives a
+ *    message; nothing is enqueued.  Per-ray run-time conditions are reported
+ *    in the optional ray_status array, never by aborting.
+ *  - Lengths (box size, observer, chi values) share one unit, e.g. Mpc/h.
+ *    Internally they are converted to base-cell units with the FP64 divisions
+ *    h0 = L / n_base, o~ = o / h0, chi~ = chi / h0; a level-l cell has size
+ *    2^-l.  kappa is unchanged by that rescaling.  Pass Phi already divided by
+ *    c^2 (or set kappa_scale) -- the 1/c^2 of Eq. (kappa).
+ *  - Arrays of cells are [z][y][x] with x fastest.  Tensor components are
+ *    ordered xx, yy, zz, xy, xz, yz.
+ *  - Crossing rule (the paper's Eq. (disttocross) picks the face reached
+ *    first; ties and the ownership of points on faces are not stated there):
+ *    with t_a(P) = (P - o~_a) * (1 / n_a) evaluated in FP64 without
+ *    contraction, a ray is in slab m of axis a when t_exit < chi <= t_entry;
+ *    the exit point is chi_B = max(chi_lo, t_exit,x, t_exit,y, t_exit,z), and
+ *    every axis whose exit parameter equals chi_B is stepped together, so no
+ *    zero-length piece is ever produced.
+ */
+#ifndef RAYRAMSES_H
+#define RAYRAMSES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A hipStream_t. */
+typedef struct ihipStream_t* rr_stream;
+
+typedef enum {
+  RR_OK = 0,
+  RR_ERR_INVALID_ARG = -1,   /* null pointer, bad size, chi window not 0 <= lo < hi <= chi_s, ... */
+  RR_ERR_UNSUPPORTED = -2,   /* valid request this build does not implement */
+  RR_ERR_OOM = -3,           /* device allocation failed (only in create / first-use calls) */
+  RR_ERR_HIP = -4,           /* a HIP runtime call failed; message holds hipGetErrorString */
+  RR_ERR_OCTREE = -5,        /* octree malformed or not 2:1 balanced over faces, edges, corners */
+  RR_ERR_DOMAIN = -6,        /* open-boundary grid too small for the stencil */
+  RR_ERR_NONFINITE = -7,     /* non-finite observer / direction / chi */
+  RR_ERR_CAPACITY = -8,      /* graph or bundle cache full, or capture in a state that forbids the call */
+} rr_status;
+
+typedef enum { RR_GRID_UNIFORM = 0, RR_GRID_OCTREE = 1 } rr_grid_kind;
+/* RR_FIELD_DELTA (the density term of the paper's Method A, Eq. kappa2) is
+ * accepted by the descriptor but returns RR_ERR_UNSUPPORTED. */
+typedef enum { RR_FIELD_PHI = 0, RR_FIELD_DELTA = 1 } rr_field_kind;
+/* PERIODIC: the grid is one period of a replicated box (the paper's tiled
+ * boxes, Sec. III B, with one realization).  OPEN: no wrap; cells on the two
+ * outer layers only feed stencils, and a ray entering a cell outside
+ * [2, n-3]^3 stops with RR_RAY_OUT_OF_DOMAIN. */
+typedef enum { RR_BOUNDARY_PERIODIC = 0, RR_BOUNDARY_OPEN = 1 } rr_boundary;
+/* FP64: tensor, vertex values and per-cell integrals in double.
+ * FP32_KAHAN: tensor and per-cell integrals in float, kappa accumulated with
+ * Kahan compensation; crossing parameters and chi bookkeeping stay FP64. */
+typedef enum { RR_PREC_FP64 = 0, RR_PREC_FP32_KAHAN = 1 } rr_precision;
+typedef enum { RR_F32 = 0, RR_F64 = 1 } rr_dtype;
+/* Integrand: kappa (Eq. kappa), gamma_1 (Eq. gamma1), gamma_2 (Eq. gamma2 with
+ * the mixed projection e_phi^T T e_theta). */
+typedef enum { RR_Q_KAPPA = 0, RR_Q_GAMMA1 = 1, RR_Q_GAMMA2 = 2 } rr_quantity;
+/* Per-cell integral: trilinear vertex reconstruction (Eq. Iclensing) or the
+ * nearest-grid-point value of the cell centre (Eq. Iclensing_ngp). */
+typedef enum { RR_INTEGRAL_TRILINEAR = 0, RR_INTEGRAL_NGP = 1 } rr_integral;
+
+/* Per-ray status written to ray_status. */
+enum {
+  RR_RAY_OK = 0,
+  RR_RAY_OUT_OF_DOMAIN = 1,  /* open grid: left [2, n-3]^3 */
+  RR_RAY_MAX_STEPS = 2,      /* hit rr_trace_params.max_crossings */
+  RR_RAY_NONFINITE = 3,      /* the accumulated value is NaN or Inf */
+  RR_RAY_BAD_DIRECTION = 4,  /* direction not finite or | |n|^2 - 1 | > 1e-9: ray skipped */
+};
+
+/* Description of one potential field (paper Sec. III A: a domain-level grid of
+ * n_base^3 cells, refined into octs of 8 cells each, 2:1 balanced). */
+typedef struct {
+  int32_t kind;          /* rr_grid_kind */
+  int32_t field;         /* rr_field_kind */
+  int32_t boundary;      /* rr_boundary; octrees must be PERIODIC */
+  int32_t dtype;         /* rr_dtype of values */
+  int32_t n_base;        /* base cells per side, >= 4 (open: >= 6) */
+  int32_t max_level;     /* octree: deepest level present (0..4); uniform: 0 */
+  double box_size;       /* L: side of the base grid */
+  /* device.  Uniform: n_base^3 values, [z][y][x].  Octree: one value per cell,
+   * leaf and refined cells alike: base cells 0..n_base^3-1, then oct k owns
+   * cells n_base^3 + 8k + (ix + 2 iy + 4 iz); octs in breadth-first order
+   * (all octs of level l before those of level l+1, each level ordered by
+   * parent cell index). */
+  const void* values;
+  const int32_t* child_oct;  /* device, octree: n_cells entries, oct index or -1 */
+  int64_t n_cells;           /* octree: n_base^3 + 8 * n_octs */
+} rr_field_desc;
+
+typedef struct rr_tensor_s* rr_tensor;
+typedef struct rr_plan_s* rr_plan;
+
+/* Allocate the vertex-tensor storage for a field of this shape and precision.
+ * Uniform: one 6-component tensor per vertex (vertex (i,j,k) is the lower
+ * corner of cell (i,j,k)).  Octree: the child_oct array is copied to the host
+ * once to lay out levels and to check 2:1 balance (RR_ERR_OCTREE otherwise);
+ * the tensor keeps the device child_oct pointer, which must stay valid while
+ * the tensor is used.  Synchronous; allocates device memory. */
+rr_status rr_tensor_create(const rr_field_desc* f, rr_precision p, rr_tensor* out);
+rr_status rr_tensor_destroy(rr_tensor t);
+
+/* Tidal tensor at cell centres by central finite differences (Eq.
+ * tidalexample, cell size of the cell's own level) and its interpolation to
+ * cell vertices (Sec. III F).  Octree cells whose stencil is incomplete at
+ * their level take the trilinear interpolation of the coarser level's
+ * component (Sec. IV C, second approach).  f must describe the same grid as
+ * at rr_tensor_create; values may change between calls (one call per N-body
+ * step).  Asynchronous on s; no allocation. */
+rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s);
+
+/* Device layout of a built tensor, for inspection.  Uniform: *data holds
+ * n_base^3 records of `stride` bytes, components first (float or double by
+ * precision).  Octree: n_cells records of 8 corners x 6 components
+ * (corner v = ix + 2 iy + 4 iz), meaningful for leaf cells. */
+rr_status rr_tensor_layout(rr_tensor t, const void** data, int64_t* n_records,
+                           int32_t* record_bytes, int32_t* precision);
+
+/* A bundle of rays sharing a source distance and a chi window: the rays of a
+ * flat-sky map of nx by ny directions (Eqs. txty, rayid: ray id = iy*nx + ix).
+ * Each wavefront of the march holds an 8 x 8 tile of the map. */
+typedef struct {
+  int64_t ray_offset;    /* index of this bundle's first ray in the output arrays */
+  int64_t n_rays;        /* nx * ny; 0 is allowed (empty bundle) */
+  const double* dir;     /* device: n_rays x 3 FP64 unit vectors, observer -> source */
+  int32_t nx, ny;
+  double chi_s;          /* source distance (defines g) */
+  double chi_hi, chi_lo; /* this call's chi window, 0 <= chi_lo < chi_hi <= chi_s */
+} rr_bundle;
+
+typedef struct {
+  double observer[3];        /* observer position in the periodic box */
+  double kappa_scale;        /* multiplies every per-cell integral */
+  int32_t precision;         /* rr_precision, must equal the tensor's */
+  int32_t quantity;          /* rr_quantity */
+  int32_t integral;          /* rr_integral */
+  int32_t persistent;        /* 0: one wavefront per tile; 1: persistent
+                                workgroups pulling tiles from a device queue;
+                                -1: let the plan's tuner choose */
+  int64_t max_crossings;     /* per ray per call; <= 0 means no limit */
+  /* Optional debug outputs (device, NULL to skip), indexed like kappa:
+   * crossing_hash: FNV-1a (64 bit) over the little-endian bytes of every
+   *   piece (int64 cell id, IEEE bits of chi_A~, IEEE bits of chi_B~), chi in
+   *   base-cell units; the uniform cell id is (z*n + y)*n + x after wrapping,
+   *   the octree id is the leaf's cell index;
+   * crossing_count: number of pieces;
+   * crossing_log: up to log_stride records {int64 cell, double chi_A, double
+   *   chi_B} per ray at crossing_log + 24 * log_stride * ray. */
+  uint64_t* crossing_hash;
+  int64_t* crossing_count;
+  void* crossing_log;
+  int64_t log_stride;
+} rr_trace_params;
+
+/* A plan owns the work queue, the device copies of bundle tables, tuning
+ * results and captured graphs.  Not thread-safe: one host thread per plan. */
+rr_status rr_plan_create(rr_plan* p);
+rr_status rr_plan_destroy(rr_plan p);
+
+/* Integrate every ray of every bundle through the tensor (Eqs. sumIc, Ic,
+ * Iclensing) and ADD kappa_scale * sum of pieces to kappa[ray_offset + i].
+ *  kappa      device: FP32 (FP32_KAHAN) or FP64 (FP64) per ray, in/out.
+ *  kappa_comp device FP32 per ray, in/out Kahan compensation (FP32_KAHAN
+ *             only; NULL = start from zero and drop it at the end).  Passing
+ *             the same kappa/kappa_comp to consecutive chi segments makes the
+ *             multi-segment result equal the single-segment one to rounding.
+ *  ray_status device int32 per ray, optional, written (not accumulated).
+ * The start cell of a segment is located from chi_hi by the slab rule, so a
+ * ray's state between segments is just (kappa, kappa_comp).  The first call
+ * with a new bundle table uploads it (synchronously, outside graph capture);
+ * later calls with an identical table allocate and copy nothing. */
+rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp,
+                        const rr_bundle* bundles /* host */, int32_t n_bundles, void* kappa,
+                        float* kappa_comp, int32_t* ray_status, rr_stream s);
+
+/* Gradient of L = sum_r w_r kappa_r with respect to the potential values of
+ * a uniform periodic FP32 field: ADDS dL/dPhi to dl_dphi (device, n_base^3
+ * FP32, same layout as f->values).  kappa is linear in Phi (straight rays,
+ * Born approximation, Sec. IV A), and the result is the exact transpose of
+ * the forward chain (per-cell integral, vertex mean, finite differences),
+ * accumulated with FP32 atomics (order-dependent rounding).  Uses the
+ * tensor's storage as scratch: rebuild the tensor before the next trace.
+ * Octree fields return RR_ERR_UNSUPPORTED. */
+rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
+                                const rr_trace_params* tp, const rr_bundle* bundles,
+                                int32_t n_bundles, const float* dl_dkappa, float* dl_dphi,
+                                rr_stream s);
+
+/* Capture every library call enqueued on s between begin and end into one
+ * HIP graph owned by the plan (replaces any previous one), then replay it
+ * with rr_graph_launch.  Bundle tables must have been uploaded before begin.
+ * The graph holds kernel nodes only (queue counters are reset by a kernel). */
+rr_status rr_graph_begin(rr_plan p, rr_stream s);
+rr_status rr_graph_end(rr_plan p, rr_stream s);
+rr_status rr_graph_launch(rr_plan p, rr_stream s);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* rr_last_error(void);
+/* Library version: major * 10000 + minor * 100 + patch. */
+int32_t rr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAYRAMSES_H */

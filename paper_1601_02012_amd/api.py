@@ -1,0 +1,340 @@
+"""Python binding of librayramses (argument marshalling only).
+
+Every step of the ray-tracing path runs in the HIP kernels of the library;
+PyTorch supplies device memory and the current HIP stream.  Names follow the
+C ABI in include/rayramses.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from ._abi import RRError  # noqa: F401  (re-export)
+
+PREC = {"fp64": A.PREC_FP64, "fp32": A.PREC_FP32_KAHAN, "fp32_kahan": A.PREC_FP32_KAHAN}
+QUANTITY = {"kappa": A.Q_KAPPA, "gamma1": A.Q_GAMMA1, "gamma2": A.Q_GAMMA2}
+
+_lib = A.lib()   # fail loudly at import if the HIP library is missing
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _prec(p):
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+class Grid:
+    """A potential field on a uniform grid or a 2:1 octree (device tensors).
+
+    values: uniform -> (n, n, n) [z][y][x]; octree -> (n_cells,) one per cell.
+    child_oct: octree only, int32 (n_cells,)."""
+
+    def __init__(self, values: torch.Tensor, box: float, *, n_base: Optional[int] = None,
+                 boundary: str = "periodic", child_oct: Optional[torch.Tensor] = None,
+                 max_level: int = 0):
+        if values.dtype not in (torch.float32, torch.float64):
+            raise TypeError("values must be float32 or float64")
+        self.values = values.contiguous()
+        self.box = float(box)
+        self.octree = child_oct is not None
+        self.child_oct = child_oct.contiguous() if child_oct is not None else None
+        if self.octree:
+            if n_base is None:
+                raise ValueError("octree grids need n_base")
+            self.n = int(n_base)
+        else:
+            self.n = int(values.shape[0]) if n_base is None else int(n_base)
+        self.boundary = A.BOUNDARY_OPEN if boundary == "open" else A.BOUNDARY_PERIODIC
+        self.max_level = int(max_level)
+
+    def desc(self) -> A.FieldDesc:
+        d = A.FieldDesc()
+        d.kind = A.GRID_OCTREE if self.octree else A.GRID_UNIFORM
+        d.field = A.FIELD_PHI
+        d.boundary = self.boundary
+        d.dtype = A.F32 if self.values.dtype == torch.float32 else A.F64
+        d.n_base = self.n
+        d.max_level = self.max_level
+        d.box_size = self.box
+        d.values = _ptr(self.values)
+        d.child_oct = _ptr(self.child_oct)
+        d.n_cells = int(self.values.numel()) if self.octree else 0
+        return d
+
+
+class TidalTensor:
+    """Library-owned vertex tensor of a grid (rr_tensor)."""
+
+    def __init__(self, grid: Grid, precision="fp32"):
+        self.grid = grid
+        self.precision = _prec(precision)
+        h = C.c_void_p()
+        d = grid.desc()
+        A.check("rr_tensor_create", _lib.rr_tensor_create(C.byref(d), self.precision, C.byref(h)))
+        self.handle = h
+
+    def build(self, grid: Optional[Grid] = None, stream=None) -> "TidalTensor":
+        g = grid if grid is not None else self.grid
+        self.grid = g
+        d = g.desc()
+        A.check("rr_build_tidal_tensor",
+                _lib.rr_build_tidal_tensor(self.handle, C.byref(d), _stream(stream)))
+        return self
+
+    def layout(self):
+        p = C.c_void_p()
+        n = C.c_int64()
+        rb = C.c_int32()
+        pr = C.c_int32()
+        A.check("rr_tensor_layout", _lib.rr_tensor_layout(self.handle, C.byref(p), C.byref(n),
+                                                          C.byref(rb), C.byref(pr)))
+        return p.value, n.value, rb.value, pr.value
+
+    def to_torch(self) -> torch.Tensor:
+        """Copy of the records as a (n_records, record_words) device tensor."""
+        ptr, n, rb, pr = self.layout()
+        dt = torch.float32 if pr == A.PREC_FP32_KAHAN else torch.float64
+        words = rb // (4 if dt == torch.float32 else 8)
+        out = torch.empty((n, words), dtype=dt, device="cuda")
+        _memcpy_d2d(out.data_ptr(), ptr, n * rb)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.rr_tensor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def _memcpy_d2d(dst: int, src: int, nbytes: int):
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        _hip.hipMemcpyAsync.restype = C.c_int
+    err = _hip.hipMemcpyAsync(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 3,
+                              _stream())
+    if err != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({err})")
+
+
+class Plan:
+    """Work queue, bundle-table cache and captured graph (rr_plan)."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        A.check("rr_plan_create", _lib.rr_plan_create(C.byref(h)))
+        self.handle = h
+
+    def graph_begin(self, stream=None):
+        A.check("rr_graph_begin", _lib.rr_graph_begin(self.handle, _stream(stream)))
+
+    def graph_end(self, stream=None):
+        A.check("rr_graph_end", _lib.rr_graph_end(self.handle, _stream(stream)))
+
+    def graph_launch(self, stream=None):
+        A.check("rr_graph_launch", _lib.rr_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.rr_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class RayBundle:
+    """Rays of one nx-by-ny map (device FP64 unit directions, ray id = iy*nx+ix)."""
+    dirs: torch.Tensor
+    nx: int
+    ny: int
+    chi_s: float
+    chi_hi: float
+    chi_lo: float
+    ray_offset: int = 0
+
+    @property
+    def n_rays(self):
+        return self.nx * self.ny
+
+    def window(self, chi_hi: float, chi_lo: float) -> "RayBundle":
+        return RayBundle(self.dirs, self.nx, self.ny, self.chi_s, chi_hi, chi_lo, self.ray_offset)
+
+
+def _bundle_array(bundles: Sequence[RayBundle]):
+    arr = (A.Bundle * max(1, len(bundles)))()
+    for i, b in enumerate(bundles):
+        if b.n_rays:
+            if b.dirs.dtype != torch.float64 or b.dirs.shape[-1] != 3:
+                raise TypeError("bundle directions must be float64 (n, 3)")
+            if b.dirs.numel() != 3 * b.n_rays:
+                raise ValueError("bundle directions do not match nx*ny")
+        arr[i].ray_offset = b.ray_offset
+        arr[i].n_rays = b.n_rays
+        arr[i].dir = _ptr(b.dirs) if b.n_rays else None
+        arr[i].nx = b.nx
+        arr[i].ny = b.ny
+        arr[i].chi_s = b.chi_s
+        arr[i].chi_hi = b.chi_hi
+        arr[i].chi_lo = b.chi_lo
+    return arr
+
+
+def _params(observer, precision, quantity="kappa", kappa_scale=1.0, persistent=-1,
+            max_crossings=0, hash=None, count=None, log=None, log_stride=0):
+    tp = A.TraceParams()
+    for k in range(3):
+        tp.observer[k] = float(observer[k])
+    tp.kappa_scale = float(kappa_scale)
+    tp.precision = precision
+    tp.quantity = QUANTITY[quantity] if isinstance(quantity, str) else int(quantity)
+    tp.integral = A.INTEGRAL_TRILINEAR
+    tp.persistent = int(persistent)
+    tp.max_crossings = int(max_crossings)
+    tp.crossing_hash = _ptr(hash)
+    tp.crossing_count = _ptr(count)
+    tp.crossing_log = _ptr(log)
+    tp.log_stride = int(log_stride)
+    return tp
+
+
+LOG_DTYPE = np.dtype([("cell", np.int64), ("chi_a", np.float64), ("chi_b", np.float64)])
+
+
+@dataclass
+class TraceOutput:
+    kappa: torch.Tensor
+    kappa_comp: Optional[torch.Tensor]
+    status: Optional[torch.Tensor]
+    hash: Optional[torch.Tensor] = None
+    count: Optional[torch.Tensor] = None
+    log: Optional[torch.Tensor] = None
+
+
+def total_rays(bundles: Sequence[RayBundle]) -> int:
+    return max([b.ray_offset + b.n_rays for b in bundles] + [0])
+
+
+def trace(plan: Plan, tensor: TidalTensor, bundles: Sequence[RayBundle], observer, *,
+          kappa: Optional[torch.Tensor] = None, kappa_comp: Optional[torch.Tensor] = None,
+          status: Optional[torch.Tensor] = None, kappa_scale: float = 1.0, quantity="kappa",
+          persistent: int = -1, max_crossings: int = 0, debug: bool = False,
+          log_stride: int = 0, stream=None) -> TraceOutput:
+    """rr_trace_rays: add each ray's integral to ``kappa`` (allocated if None)."""
+    nr = total_rays(bundles)
+    fp32 = tensor.precision == A.PREC_FP32_KAHAN
+    dev = "cuda"
+    if kappa is None:
+        kappa = torch.zeros(nr, dtype=torch.float32 if fp32 else torch.float64, device=dev)
+    if kappa_comp is None and fp32:
+        kappa_comp = torch.zeros(nr, dtype=torch.float32, device=dev)
+    if status is None:
+        status = torch.zeros(nr, dtype=torch.int32, device=dev)
+    hsh = cnt = log = None
+    if debug:
+        hsh = torch.zeros(nr, dtype=torch.int64, device=dev)
+        cnt = torch.zeros(nr, dtype=torch.int64, device=dev)
+    if log_stride:
+        log = torch.zeros((nr, log_stride, 3), dtype=torch.float64, device=dev)
+    tp = _params(observer, tensor.precision, quantity, kappa_scale, persistent, max_crossings,
+                 hsh, cnt, log, log_stride)
+    arr = _bundle_array(bundles)
+    A.check("rr_trace_rays",
+            _lib.rr_trace_rays(plan.handle, tensor.handle, C.byref(tp), arr, len(bundles),
+                               _ptr(kappa), _ptr(kappa_comp) if fp32 else None, _ptr(status),
+                               _stream(stream)))
+    return TraceOutput(kappa, kappa_comp, status, hsh, cnt, log)
+
+
+def log_to_numpy(log: torch.Tensor) -> np.ndarray:
+    """Convert a crossing log tensor (n, stride, 3 x 8 bytes) to records."""
+    return log.cpu().numpy().view(LOG_DTYPE).reshape(log.shape[0], log.shape[1])
+
+
+def trace_adjoint(plan: Plan, tensor: TidalTensor, grid: Grid, bundles: Sequence[RayBundle],
+                  observer, dl_dkappa: torch.Tensor, *, dl_dphi: Optional[torch.Tensor] = None,
+                  kappa_scale: float = 1.0, stream=None) -> torch.Tensor:
+    """rr_trace_rays_adjoint: dL/dPhi (added to ``dl_dphi``, allocated if None)."""
+    if dl_dphi is None:
+        dl_dphi = torch.zeros_like(grid.values, dtype=torch.float32)
+    tp = _params(observer, tensor.precision, "kappa", kappa_scale, 0)
+    arr = _bundle_array(bundles)
+    d = grid.desc()
+    w = dl_dkappa.to(torch.float32).contiguous()
+    A.check("rr_trace_rays_adjoint",
+            _lib.rr_trace_rays_adjoint(plan.handle, tensor.handle, C.byref(d), C.byref(tp), arr,
+                                       len(bundles), _ptr(w), _ptr(dl_dphi), _stream(stream)))
+    return dl_dphi
+
+
+class Geometry:
+    """Non-differentiable ray geometry for :class:`RayTraceKappa`."""
+
+    def __init__(self, box: float, observer, bundles: Sequence[RayBundle], *,
+                 kappa_scale: float = 1.0, plan: Optional[Plan] = None):
+        self.box = float(box)
+        self.observer = tuple(float(x) for x in observer)
+        self.bundles = list(bundles)
+        self.kappa_scale = kappa_scale
+        self.plan = plan or Plan()
+        self._tensor = None
+
+    def tensor_for(self, grid: Grid) -> TidalTensor:
+        if self._tensor is None or self._tensor.grid.n != grid.n:
+            self._tensor = TidalTensor(grid, "fp32")
+        return self._tensor
+
+
+class RayTraceKappa(torch.autograd.Function):
+    """kappa = A(phi) on a uniform periodic FP32 grid, with the hand-written
+    adjoint (rr_trace_rays_adjoint) as backward."""
+
+    @staticmethod
+    def forward(ctx, phi: torch.Tensor, geometry: Geometry):
+        grid = Grid(phi.detach().to(torch.float32).contiguous(), geometry.box)
+        t = geometry.tensor_for(grid)
+        t.build(grid)
+        out = trace(geometry.plan, t, geometry.bundles, geometry.observer,
+                    kappa_scale=geometry.kappa_scale, persistent=0)
+        ctx.geometry = geometry
+        ctx.grid = grid
+        return out.kappa.clone()
+
+    @staticmethod
+    def backward(ctx, grad_kappa: torch.Tensor):
+        g = ctx.geometry
+        t = g.tensor_for(ctx.grid)
+        dphi = trace_adjoint(g.plan, t, ctx.grid, g.bundles, g.observer,
+                             grad_kappa.contiguous(), kappa_scale=g.kappa_scale)
+        return dphi, None

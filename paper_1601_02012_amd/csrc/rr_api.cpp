@@ -1,0 +1,460 @@
+// rr_api.cpp -- host side of the C ABI declared in include/rayramses.h:
+// argument validation, tensor and plan objects, bundle-table upload cache,
+// launch configuration and HIP graph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "rr_internal.hpp"
+#include "rr_octree.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+rr_status fail(rr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+rr_status hip_fail(hipError_t e, const char* what) {
+  return fail(RR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define RR_HIP(call, what)                   \
+  do {                                       \
+    hipError_t _e = (call);                  \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+}  // namespace
+
+struct rr_tensor_s {
+  int32_t kind = RR_GRID_UNIFORM;
+  int32_t precision = RR_PREC_FP32_KAHAN;
+  int32_t boundary = RR_BOUNDARY_PERIODIC;
+  int32_t n = 0;
+  int32_t dtype = RR_F32;
+  double box = 0.0;
+  void* data = nullptr;        // uniform: vertex records; octree: per-leaf corner blocks
+  int64_t n_records = 0;
+  int32_t record_bytes = 0;
+  void* grad = nullptr;        // adjoint workspace (allocated on first use)
+  std::unique_ptr<rr::OctreeTensor> oct;
+};
+
+namespace {
+
+struct CachedTable {
+  std::vector<rr_bundle> key;
+  int32_t n = 0;
+  double box = 0.0;
+  int32_t persistent_order = 0;
+  rr::DevBundle* dev = nullptr;
+  int64_t n_tiles = 0;
+};
+
+}  // namespace
+
+struct rr_plan_s {
+  unsigned long long* queue = nullptr;
+  std::vector<CachedTable> tables;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int cu_count = 0;
+  int waves_per_cu = 0;      // persistent occupancy target
+  int prefer_persistent = 0; // tuner result
+  int device = 0;
+};
+
+namespace {
+
+bool finite3(const double* v) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+rr_status validate_field(const rr_field_desc* f) {
+  if (!f) return fail(RR_ERR_INVALID_ARG, "field descriptor is NULL");
+  if (f->kind != RR_GRID_UNIFORM && f->kind != RR_GRID_OCTREE)
+    return fail(RR_ERR_INVALID_ARG, "unknown grid kind %d", f->kind);
+  if (f->field == RR_FIELD_DELTA)
+    return fail(RR_ERR_UNSUPPORTED, "density fields (Method A) are not implemented");
+  if (f->field != RR_FIELD_PHI) return fail(RR_ERR_INVALID_ARG, "unknown field kind %d", f->field);
+  if (f->dtype != RR_F32 && f->dtype != RR_F64)
+    return fail(RR_ERR_INVALID_ARG, "unknown dtype %d", f->dtype);
+  if (f->boundary != RR_BOUNDARY_PERIODIC && f->boundary != RR_BOUNDARY_OPEN)
+    return fail(RR_ERR_INVALID_ARG, "unknown boundary %d", f->boundary);
+  if (f->n_base < 4 || f->n_base > 4096)
+    return fail(RR_ERR_INVALID_ARG, "n_base %d outside [4, 4096]", f->n_base);
+  if (f->boundary == RR_BOUNDARY_OPEN && f->n_base < 6)
+    return fail(RR_ERR_DOMAIN, "open grid needs n_base >= 6 (two stencil layers per side)");
+  if (!(f->box_size > 0.0) || !std::isfinite(f->box_size))
+    return fail(RR_ERR_INVALID_ARG, "box_size must be positive and finite");
+  if (!f->values) return fail(RR_ERR_INVALID_ARG, "values is NULL");
+  if (f->kind == RR_GRID_OCTREE) {
+    if (f->boundary != RR_BOUNDARY_PERIODIC)
+      return fail(RR_ERR_UNSUPPORTED, "octree fields must be periodic");
+    if (!f->child_oct) return fail(RR_ERR_INVALID_ARG, "octree child_oct is NULL");
+    const int64_t nb = (int64_t)f->n_base * f->n_base * f->n_base;
+    if (f->n_cells < nb || (f->n_cells - nb) % 8 != 0)
+      return fail(RR_ERR_OCTREE, "n_cells must be n_base^3 + 8 * n_octs");
+    if (f->max_level < 0 || f->max_level > rr::kMaxLevel)
+      return fail(RR_ERR_INVALID_ARG, "max_level %d outside [0, %d]", f->max_level, rr::kMaxLevel);
+  } else if (f->max_level != 0) {
+    return fail(RR_ERR_INVALID_ARG, "uniform grids have max_level 0");
+  }
+  return RR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rr_last_error(void) { return g_err.c_str(); }
+int32_t rr_version(void) { return 10000; }
+
+rr_status rr_tensor_create(const rr_field_desc* f, rr_precision p, rr_tensor* out) {
+  if (!out) return fail(RR_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  rr_status st = validate_field(f);
+  if (st != RR_OK) return st;
+  if (p != RR_PREC_FP64 && p != RR_PREC_FP32_KAHAN)
+    return fail(RR_ERR_INVALID_ARG, "unknown precision %d", (int)p);
+  std::unique_ptr<rr_tensor_s> t(new rr_tensor_s);
+  t->kind = f->kind;
+  t->precision = p;
+  t->boundary = f->boundary;
+  t->n = f->n_base;
+  t->dtype = f->dtype;
+  t->box = f->box_size;
+  if (f->kind == RR_GRID_UNIFORM) {
+    const int64_t nv = (int64_t)f->n_base * f->n_base * f->n_base;
+    t->record_bytes = p == RR_PREC_FP32_KAHAN ? 32 : 48;
+    t->n_records = nv;
+    hipError_t e = hipMalloc(&t->data, (size_t)nv * t->record_bytes);
+    if (e != hipSuccess) return fail(RR_ERR_OOM, "vertex tensor: %s", hipGetErrorString(e));
+  } else {
+    std::string msg;
+    t->oct.reset(rr::OctreeTensor::create(f, p, &st, &msg));
+    if (!t->oct) return fail(st, "%s", msg.c_str());
+    t->data = t->oct->corners;
+    t->n_records = t->oct->n_cells;
+    t->record_bytes = t->oct->corner_record_bytes;
+  }
+  *out = t.release();
+  return RR_OK;
+}
+
+rr_status rr_tensor_destroy(rr_tensor t) {
+  if (!t) return RR_OK;
+  if (t->kind == RR_GRID_UNIFORM && t->data) (void)hipFree(t->data);
+  if (t->grad) (void)hipFree(t->grad);
+  delete t;
+  return RR_OK;
+}
+
+rr_status rr_tensor_layout(rr_tensor t, const void** data, int64_t* n_records,
+                           int32_t* record_bytes, int32_t* precision) {
+  if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  if (data) *data = t->data;
+  if (n_records) *n_records = t->n_records;
+  if (record_bytes) *record_bytes = t->record_bytes;
+  if (precision) *precision = t->precision;
+  return RR_OK;
+}
+
+rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s) {
+  if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  rr_status st = validate_field(f);
+  if (st != RR_OK) return st;
+  if (f->kind != t->kind || f->n_base != t->n || f->boundary != t->boundary)
+    return fail(RR_ERR_INVALID_ARG, "field does not match the grid the tensor was created for");
+  if (f->kind == RR_GRID_UNIFORM) {
+    RR_HIP(rr::launch_vertex_tensor_uniform(t->precision, f->dtype, f->n_base,
+                                            f->boundary == RR_BOUNDARY_OPEN, f->values, t->data,
+                                            (hipStream_t)s),
+           "vertex tensor launch");
+    return RR_OK;
+  }
+  if (f->n_cells != t->oct->n_cells || f->child_oct != t->oct->child_oct_dev)
+    return fail(RR_ERR_INVALID_ARG, "octree does not match the one the tensor was created for");
+  RR_HIP(t->oct->build(f->values, f->dtype, (hipStream_t)s), "octree tensor launch");
+  return RR_OK;
+}
+
+rr_status rr_plan_create(rr_plan* p) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan out-pointer is NULL");
+  *p = nullptr;
+  std::unique_ptr<rr_plan_s> q(new rr_plan_s);
+  RR_HIP(hipGetDevice(&q->device), "hipGetDevice");
+  hipDeviceProp_t prop;
+  RR_HIP(hipGetDeviceProperties(&prop, q->device), "hipGetDeviceProperties");
+  q->cu_count = prop.multiProcessorCount;
+  q->waves_per_cu = 16;
+  hipError_t e = hipMalloc((void**)&q->queue, 256);
+  if (e != hipSuccess) return fail(RR_ERR_OOM, "queue: %s", hipGetErrorString(e));
+  RR_HIP(hipMemset(q->queue, 0, 256), "queue init");
+  *p = q.release();
+  return RR_OK;
+}
+
+rr_status rr_plan_destroy(rr_plan p) {
+  if (!p) return RR_OK;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (auto& c : p->tables)
+    if (c.dev) (void)hipFree(c.dev);
+  if (p->queue) (void)hipFree(p->queue);
+  delete p;
+  return RR_OK;
+}
+
+namespace {
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+  return cs != hipStreamCaptureStatusNone;
+}
+
+rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle* b, int32_t nb) {
+  if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  if (!tp) return fail(RR_ERR_INVALID_ARG, "trace params are NULL");
+  if (nb < 0 || (nb > 0 && !b)) return fail(RR_ERR_INVALID_ARG, "bad bundle array");
+  if (tp->precision != t->precision)
+    return fail(RR_ERR_INVALID_ARG, "trace precision %d differs from the tensor's %d",
+                tp->precision, t->precision);
+  if (tp->quantity < RR_Q_KAPPA || tp->quantity > RR_Q_GAMMA2)
+    return fail(RR_ERR_INVALID_ARG, "unknown quantity %d", tp->quantity);
+  if (tp->integral == RR_INTEGRAL_NGP)
+    return fail(RR_ERR_UNSUPPORTED, "the NGP per-cell integral is not implemented on the GPU");
+  if (tp->integral != RR_INTEGRAL_TRILINEAR)
+    return fail(RR_ERR_INVALID_ARG, "unknown integral %d", tp->integral);
+  if (!finite3(tp->observer)) return fail(RR_ERR_NONFINITE, "observer is not finite");
+  const double h0 = t->box / (double)t->n;
+  const double cell_cap = (double)(1 << 30);
+  for (int k = 0; k < 3; ++k)
+    if (std::fabs(tp->observer[k] / h0) > cell_cap)
+      return fail(RR_ERR_INVALID_ARG, "observer is more than 2^30 cells from the origin");
+  if (!std::isfinite(tp->kappa_scale)) return fail(RR_ERR_NONFINITE, "kappa_scale not finite");
+  if (tp->log_stride < 0 || (tp->crossing_log && tp->log_stride == 0))
+    return fail(RR_ERR_INVALID_ARG, "crossing_log needs log_stride > 0");
+  for (int32_t i = 0; i < nb; ++i) {
+    const rr_bundle& x = b[i];
+    if (x.n_rays < 0 || x.ray_offset < 0)
+      return fail(RR_ERR_INVALID_ARG, "bundle %d: negative size or offset", i);
+    if (x.n_rays == 0) continue;
+    if (!x.dir) return fail(RR_ERR_INVALID_ARG, "bundle %d: dir is NULL", i);
+    if (x.nx <= 0 || x.ny <= 0 || (int64_t)x.nx * x.ny != x.n_rays)
+      return fail(RR_ERR_INVALID_ARG, "bundle %d: nx*ny (%d*%d) != n_rays (%lld)", i, x.nx, x.ny,
+                  (long long)x.n_rays);
+    if (!std::isfinite(x.chi_s) || !std::isfinite(x.chi_hi) || !std::isfinite(x.chi_lo))
+      return fail(RR_ERR_NONFINITE, "bundle %d: chi values must be finite", i);
+    if (!(x.chi_s > 0.0)) return fail(RR_ERR_INVALID_ARG, "bundle %d: chi_s must be > 0", i);
+    if (!(0.0 <= x.chi_lo && x.chi_lo < x.chi_hi && x.chi_hi <= x.chi_s))
+      return fail(RR_ERR_INVALID_ARG,
+                  "bundle %d: need 0 <= chi_lo < chi_hi <= chi_s (got %g, %g, %g)", i, x.chi_lo,
+                  x.chi_hi, x.chi_s);
+    // a unit ray crosses at most sqrt(3) * window * 2^level planes (+3 at the ends)
+    const double span = (x.chi_hi - x.chi_lo) / h0 * std::sqrt(3.0) *
+                        (double)(1 << (t->kind == RR_GRID_OCTREE ? rr::kMaxLevel : 0));
+    if (x.chi_hi / h0 > cell_cap || span > cell_cap)
+      return fail(RR_ERR_INVALID_ARG, "bundle %d: chi window spans more than 2^30 cells", i);
+  }
+  return RR_OK;
+}
+
+// Find or upload the device bundle table for (bundles, grid unit).
+rr_status get_table(rr_plan p, rr_tensor t, const rr_bundle* b, int32_t nb, int persistent,
+                    hipStream_t s, const CachedTable** out) {
+  for (auto& c : p->tables) {
+    if (c.n == t->n && c.box == t->box && c.persistent_order == persistent &&
+        (int32_t)c.key.size() == nb &&
+        (nb == 0 || std::memcmp(c.key.data(), b, sizeof(rr_bundle) * nb) == 0)) {
+      *out = &c;
+      return RR_OK;
+    }
+  }
+  if (capturing(s))
+    return fail(RR_ERR_CAPACITY,
+                "bundle table not uploaded before graph capture: run the call once first");
+  if (p->tables.size() >= 256)
+    return fail(RR_ERR_CAPACITY, "plan holds 256 bundle tables already");
+  const double h0 = t->box / (double)t->n;
+  std::vector<int32_t> order(nb);
+  for (int32_t i = 0; i < nb; ++i) order[i] = i;
+  if (persistent) {
+    // longest-processing-time first: the chi window sets the steps per ray
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      return (b[x].chi_hi - b[x].chi_lo) > (b[y].chi_hi - b[y].chi_lo);
+    });
+  }
+  std::vector<rr::DevBundle> host(std::max(nb, 1));
+  int64_t tiles = 0;
+  for (int32_t k = 0; k < nb; ++k) {
+    const rr_bundle& x = b[order[k]];
+    rr::DevBundle& d = host[k];
+    d.dir = x.dir;
+    d.ray_offset = x.ray_offset;
+    d.n_rays = x.n_rays;
+    d.nx = x.n_rays ? x.nx : 0;
+    d.ny = x.n_rays ? x.ny : 0;
+    d.tiles_x = (d.nx + 7) / 8;
+    d.tiles_y = (d.ny + 7) / 8;
+    d.tile_begin = tiles;
+    d.chi_s = x.chi_s / h0;
+    d.chi_hi = x.chi_hi / h0;
+    d.chi_lo = x.chi_lo / h0;
+    tiles += (int64_t)d.tiles_x * d.tiles_y;
+  }
+  CachedTable c;
+  c.key.assign(b, b + nb);
+  c.n = t->n;
+  c.box = t->box;
+  c.persistent_order = persistent;
+  c.n_tiles = tiles;
+  hipError_t e = hipMalloc((void**)&c.dev, sizeof(rr::DevBundle) * host.size());
+  if (e != hipSuccess) return fail(RR_ERR_OOM, "bundle table: %s", hipGetErrorString(e));
+  RR_HIP(hipMemcpy(c.dev, host.data(), sizeof(rr::DevBundle) * host.size(),
+                   hipMemcpyHostToDevice),
+         "bundle table upload");
+  p->tables.push_back(std::move(c));
+  *out = &p->tables.back();
+  return RR_OK;
+}
+
+}  // namespace
+
+rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
+                        int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
+                        rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  rr_status st = validate_trace(t, tp, bundles, n_bundles);
+  if (st != RR_OK) return st;
+  if (!kappa) return fail(RR_ERR_INVALID_ARG, "kappa is NULL");
+  if (kappa_comp && t->precision != RR_PREC_FP32_KAHAN)
+    return fail(RR_ERR_INVALID_ARG, "kappa_comp is only used by FP32_KAHAN");
+  if (tp->quantity != RR_Q_KAPPA && t->kind == RR_GRID_OCTREE)
+    return fail(RR_ERR_UNSUPPORTED, "shear on octrees is not implemented");
+  const hipStream_t hs = (hipStream_t)s;
+  const int persistent = tp->persistent < 0 ? p->prefer_persistent : (tp->persistent ? 1 : 0);
+  const CachedTable* tab = nullptr;
+  st = get_table(p, t, bundles, n_bundles, persistent, hs, &tab);
+  if (st != RR_OK) return st;
+  if (tab->n_tiles == 0) return RR_OK;
+
+  rr::TraceArgs a{};
+  a.bundles = tab->dev;
+  a.n_bundles = n_bundles;
+  a.n_tiles = tab->n_tiles;
+  const double h0 = t->box / (double)t->n;
+  for (int k = 0; k < 3; ++k) a.o[k] = tp->observer[k] / h0;
+  a.kappa_scale = tp->kappa_scale;
+  a.n = t->n;
+  a.open = t->boundary == RR_BOUNDARY_OPEN;
+  a.quantity = tp->quantity;
+  a.integral = tp->integral;
+  a.max_crossings = tp->max_crossings;
+  a.kappa = kappa;
+  a.kappa_comp = kappa_comp;
+  a.status = ray_status;
+  a.hash = tp->crossing_hash;
+  a.count = tp->crossing_count;
+  a.log = tp->crossing_log;
+  a.log_stride = tp->log_stride;
+  a.queue = p->queue;
+  const int grid_waves = p->cu_count * p->waves_per_cu;
+  if (persistent) RR_HIP(rr::launch_queue_reset(p->queue, hs), "queue reset");
+  if (t->kind == RR_GRID_UNIFORM) {
+    RR_HIP(rr::launch_march_uniform(t->precision, t->data, a, persistent, 256, grid_waves, hs),
+           "march launch");
+  } else {
+    RR_HIP(t->oct->march(a, persistent, grid_waves, hs), "octree march launch");
+  }
+  return RR_OK;
+}
+
+rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
+                                const rr_trace_params* tp, const rr_bundle* bundles,
+                                int32_t n_bundles, const float* dl_dkappa, float* dl_dphi,
+                                rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  rr_status st = validate_trace(t, tp, bundles, n_bundles);
+  if (st != RR_OK) return st;
+  st = validate_field(f);
+  if (st != RR_OK) return st;
+  if (t->kind != RR_GRID_UNIFORM || f->kind != RR_GRID_UNIFORM)
+    return fail(RR_ERR_UNSUPPORTED, "the adjoint is implemented for uniform grids only");
+  if (t->boundary != RR_BOUNDARY_PERIODIC)
+    return fail(RR_ERR_UNSUPPORTED, "the adjoint is implemented for periodic grids only");
+  if (t->precision != RR_PREC_FP32_KAHAN || f->dtype != RR_F32)
+    return fail(RR_ERR_UNSUPPORTED, "the adjoint takes an FP32 field and an FP32 tensor");
+  if (tp->quantity != RR_Q_KAPPA)
+    return fail(RR_ERR_UNSUPPORTED, "the adjoint is implemented for kappa only");
+  if (f->n_base != t->n) return fail(RR_ERR_INVALID_ARG, "field and tensor grids differ");
+  if (!dl_dkappa || !dl_dphi) return fail(RR_ERR_INVALID_ARG, "gradient pointers are NULL");
+  const hipStream_t hs = (hipStream_t)s;
+  const CachedTable* tab = nullptr;
+  st = get_table(p, t, bundles, n_bundles, 0, hs, &tab);
+  if (st != RR_OK) return st;
+  const int64_t nv = (int64_t)t->n * t->n * t->n;
+  if (!t->grad) {
+    if (capturing(hs)) return fail(RR_ERR_CAPACITY, "first adjoint call inside a capture");
+    hipError_t e = hipMalloc(&t->grad, (size_t)nv * 8 * sizeof(float));
+    if (e != hipSuccess) return fail(RR_ERR_OOM, "adjoint workspace: %s", hipGetErrorString(e));
+  }
+  rr::TraceArgs a{};
+  a.bundles = tab->dev;
+  a.n_bundles = n_bundles;
+  a.n_tiles = tab->n_tiles;
+  const double h0 = t->box / (double)t->n;
+  for (int k = 0; k < 3; ++k) a.o[k] = tp->observer[k] / h0;
+  a.kappa_scale = tp->kappa_scale;
+  a.n = t->n;
+  a.open = 0;
+  a.quantity = RR_Q_KAPPA;
+  a.max_crossings = tp->max_crossings;
+  RR_HIP(rr::launch_adjoint_uniform(a, dl_dkappa, (float*)t->grad, dl_dphi, hs), "adjoint launch");
+  return RR_OK;
+}
+
+rr_status rr_graph_begin(rr_plan p, rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  if (!s) return fail(RR_ERR_INVALID_ARG, "graph capture needs a non-default stream");
+  if (capturing((hipStream_t)s)) return fail(RR_ERR_CAPACITY, "stream is already capturing");
+  RR_HIP(hipStreamBeginCapture((hipStream_t)s, hipStreamCaptureModeThreadLocal), "begin capture");
+  return RR_OK;
+}
+
+rr_status rr_graph_end(rr_plan p, rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  hipGraph_t g = nullptr;
+  RR_HIP(hipStreamEndCapture((hipStream_t)s, &g), "end capture");
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = g;
+  RR_HIP(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0), "graph instantiate");
+  return RR_OK;
+}
+
+rr_status rr_graph_launch(rr_plan p, rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  if (!p->exec) return fail(RR_ERR_INVALID_ARG, "no graph captured on this plan");
+  RR_HIP(hipGraphLaunch(p->exec, (hipStream_t)s), "graph launch");
+  return RR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// rr_internal.hpp -- data shared by the host layer and the HIP kernels of
+// librayramses.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rayramses.h"
+
+namespace rr {
+
+// Base-cell units: h0 = L / n, o~ = o / h0, chi~ = chi / h0 (host FP64 divides).
+struct DevBundle {
+  const double* dir;   // n_rays x 3
+  int64_t ray_offset;
+  int64_t n_rays;
+  int32_t nx, ny;
+  int32_t tiles_x, tiles_y;
+  int64_t tile_begin;  // prefix over bundles in launch order
+  double chi_s, chi_hi, chi_lo;  // base-cell units
+};
+
+struct TraceArgs {
+  const DevBundle* bundles;
+  int32_t n_bundles;
+  int64_t n_tiles;           // total 8x8 tiles over all bundles
+  double o[3];               // observer, base-cell units
+  double kappa_scale;
+  int32_t n;                 // base cells per side
+  int32_t open;              // RR_BOUNDARY_OPEN
+  int32_t quantity;
+  int32_t integral;
+  int64_t max_crossings;
+  // outputs
+  void* kappa;
+  float* kappa_comp;
+  int32_t* status;
+  uint64_t* hash;
+  int64_t* count;
+  void* log;
+  int64_t log_stride;
+  // work queue (persistent mode)
+  unsigned long long* queue;
+};
+
+// Uniform vertex tensor record: FP32 -> 8 floats (6 used, 32 B, two 16-byte
+// loads); FP64 -> 6 doubles (48 B, three 16-byte loads).
+template <typename Real>
+struct VertexRecord;
+template <>
+struct VertexRecord<float> {
+  static constexpr int kWords = 8;
+};
+template <>
+struct VertexRecord<double> {
+  static constexpr int kWords = 6;
+};
+
+// host launchers (defined in the .hip files)
+hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int open,
+                                        const void* phi, void* tv, hipStream_t s);
+hipError_t launch_march_uniform(int precision, const void* tv, const TraceArgs& a, int persistent,
+                                int block, int grid_waves, hipStream_t s);
+hipError_t launch_queue_reset(unsigned long long* q, hipStream_t s);
+
+}  // namespace rr

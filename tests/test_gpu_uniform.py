@@ -1,0 +1,281 @@
+"""GPU parity of the uniform-grid path against the FP64 oracle.
+
+Bars: crossing lists bit-exact (per-ray FNV-1a hash, counts, and full logs on
+a subset); FP64 kappa to 1e-11 of the map's scale; FP32-Kahan kappa within
+max(1e-5 |kappa|, 1e-7) of the oracle for every ray."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1601_02012_amd import inputs as I
+from tests._cases import gpu_bundle, gpu_grid, hashes_u64, kappa_tolerance_ok, small_periodic_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1601_02012_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def plan(api):
+    return api.Plan()
+
+
+def _oracle_trace(oracle, n, box, obs, dirs, chis, hi, lo, phi, **kw):
+    return oracle.trace_uniform(n, box, obs, dirs, chis, hi, lo, phi=phi, **kw)
+
+
+# ------------------------------------------------------------- tensor build --
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vertex_tensor_matches_oracle(api, oracle, prec):
+    import torch
+    rng = np.random.default_rng(1)
+    for n in (8, 33, 70):                      # ragged against the 64x4x4 / 32x4x4 tiles
+        phi = rng.normal(size=(n, n, n))
+        if prec == "fp32":
+            phi = phi.astype(np.float32)
+        g = gpu_grid(api, phi, float(n))
+        t = api.TidalTensor(g, prec).build()
+        got = t.to_torch()[:, :6].double().cpu().numpy()
+        ref = oracle.vertex_tensor(phi.astype(np.float64))
+        scale = np.abs(ref).max()
+        tol = 1e-13 if prec == "fp64" else 2e-6
+        np.testing.assert_allclose(got, ref, atol=tol * scale, rtol=0)
+        t.close()
+
+
+def test_vertex_tensor_open_boundary_nan_layers(api, oracle):
+    n = 12
+    rng = np.random.default_rng(2)
+    phi = rng.normal(size=(n, n, n))
+    g = gpu_grid(api, phi, float(n), boundary="open")
+    t = api.TidalTensor(g, "fp64").build()
+    got = t.to_torch()[:, :6].cpu().numpy()
+    ref = oracle.vertex_tensor(phi, open_boundary=True)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    np.testing.assert_allclose(got[ok], ref[ok], atol=1e-13 * np.abs(ref[ok]).max())
+
+
+# ------------------------------------------------------------- config 1 -----
+@pytest.fixture(scope="module")
+def c1():
+    return I.config1()
+
+
+def test_config1_fp64_crossings_bit_exact(api, oracle, plan, c1):
+    """64^3 FP64 field, 128^2 rays over 2x2 deg from the box corner: every
+    ray's crossing list is identical to the oracle's; kappa to 1e-11."""
+    b = c1.bundles[0]
+    g = gpu_grid(api, c1.phi, c1.box)
+    t = api.TidalTensor(g, "fp64").build()
+    gb = gpu_bundle(api, b.dirs, b.nx, b.ny, b.chi_s, b.chi_hi, b.chi_lo)
+    out = api.trace(plan, t, [gb], c1.observer, debug=True)
+    ref = _oracle_trace(oracle, c1.n, c1.box, c1.observer, b.dirs, b.chi_s, b.chi_hi, b.chi_lo,
+                        c1.phi)
+    assert np.array_equal(out.count.cpu().numpy(), ref.ncross)
+    assert np.array_equal(hashes_u64(out.hash), ref.hash)
+    assert np.all(out.status.cpu().numpy() == 0)
+    k = out.kappa.cpu().numpy()
+    np.testing.assert_allclose(k, ref.kappa, rtol=0, atol=1e-11 * np.abs(ref.kappa).max())
+
+
+def test_config1_crossing_logs_subset(api, oracle, plan, c1):
+    b = c1.bundles[0]
+    sel = np.arange(0, b.nx * b.ny, 997)
+    dirs = b.dirs[sel]
+    g = gpu_grid(api, c1.phi, c1.box)
+    t = api.TidalTensor(g, "fp64").build()
+    gb = gpu_bundle(api, dirs, len(sel), 1, b.chi_s, b.chi_hi, b.chi_lo)
+    out = api.trace(plan, t, [gb], c1.observer, debug=True, log_stride=128)
+    ref = _oracle_trace(oracle, c1.n, c1.box, c1.observer, dirs, b.chi_s, b.chi_hi, b.chi_lo,
+                        c1.phi, log_stride=128)
+    got = api.log_to_numpy(out.log)
+    for k in range(len(sel)):
+        m = ref.ncross[k]
+        assert np.array_equal(got[k][:m]["cell"], ref.log[k][:m]["cell"])
+        assert np.array_equal(got[k][:m]["chi_a"], ref.log[k][:m]["chi_a"])
+        assert np.array_equal(got[k][:m]["chi_b"], ref.log[k][:m]["chi_b"])
+
+
+def test_config1_fp32_kahan_within_tolerance(api, oracle, plan, c1):
+    b = c1.bundles[0]
+    phi32 = c1.phi.astype(np.float32)
+    g = gpu_grid(api, phi32, c1.box)
+    t = api.TidalTensor(g, "fp32").build()
+    gb = gpu_bundle(api, b.dirs, b.nx, b.ny, b.chi_s, b.chi_hi, b.chi_lo)
+    out = api.trace(plan, t, [gb], c1.observer, debug=True)
+    ref = _oracle_trace(oracle, c1.n, c1.box, c1.observer, b.dirs, b.chi_s, b.chi_hi, b.chi_lo,
+                        phi32.astype(np.float64))
+    assert np.array_equal(hashes_u64(out.hash), ref.hash)
+    ok, worst = kappa_tolerance_ok(out.kappa.cpu().numpy().astype(np.float64), ref.kappa)
+    assert ok, worst
+
+
+# --------------------------------------------------- ragged / bundles / edges --
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ragged_bundles_offsets_and_empty(api, oracle, plan, prec):
+    """Three bundles (ragged 37x13 and 5x3 maps, one empty) with their own chi
+    windows, source distances and output offsets."""
+    n, box = 32, 64.0
+    phi, dirs = small_periodic_case(n=n, box=box)
+    if prec == "fp32":
+        phi = phi.astype(np.float32)
+    fov = math.radians(7.0)
+    dirs2 = I.fov_directions((-0.3, 0.2, 1.0), fov, fov, 5, 3)
+    g = gpu_grid(api, phi, box)
+    t = api.TidalTensor(g, prec).build()
+    b1 = gpu_bundle(api, dirs, 37, 13, 90.0, 80.0, 3.0, offset=0)
+    b2 = gpu_bundle(api, dirs2, 5, 3, 150.0, 149.0, 0.0, offset=37 * 13 + 10)
+    import torch
+    b3 = api.RayBundle(torch.zeros((0, 3), dtype=torch.float64, device="cuda"), 0, 0, 1.0, 1.0,
+                       0.0, 0)
+    obs = (3.3, -2.0, 1.5)
+    out = api.trace(plan, t, [b1, b3, b2], obs, debug=True)
+    k = out.kappa.cpu().numpy().astype(np.float64)
+    assert k.shape[0] == 37 * 13 + 10 + 15
+    assert np.all(k[37 * 13:37 * 13 + 10] == 0)              # gap untouched
+    for dd, nr, off, chis, hi, lo in [(dirs, 37 * 13, 0, 90.0, 80.0, 3.0),
+                                      (dirs2, 15, 37 * 13 + 10, 150.0, 149.0, 0.0)]:
+        ref = oracle.trace_uniform(n, box, obs, dd, chis, hi, lo, phi=phi.astype(np.float64))
+        assert np.array_equal(hashes_u64(out.hash)[off:off + nr], ref.hash)
+        if prec == "fp64":
+            np.testing.assert_allclose(k[off:off + nr], ref.kappa, rtol=0,
+                                       atol=1e-11 * np.abs(ref.kappa).max())
+        else:
+            ok, worst = kappa_tolerance_ok(k[off:off + nr], ref.kappa)
+            assert ok, worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_segments_resume_equals_single_pass(api, oracle, plan, prec):
+    """20 chi segments with the (kappa, kappa_comp) state carried between
+    calls equal one pass (Eq. sumIc), and each segment's crossings match."""
+    n, box = 32, 64.0
+    phi, dirs = small_periodic_case(seed=4, n=n, box=box, nx=16, ny=16)
+    if prec == "fp32":
+        phi = phi.astype(np.float32)
+    g = gpu_grid(api, phi, box)
+    t = api.TidalTensor(g, prec).build()
+    obs = (0.0, 0.0, 0.0)
+    chis = 120.0
+    edges = np.linspace(120.0, 0.0, 21)
+    import torch
+    one = api.trace(plan, t, [gpu_bundle(api, dirs, 16, 16, chis, chis, 0.0)], obs)
+    kap = torch.zeros(256, dtype=one.kappa.dtype, device="cuda")
+    comp = torch.zeros(256, dtype=torch.float32, device="cuda") if prec == "fp32" else None
+    for a, b in zip(edges[:-1], edges[1:]):
+        seg = api.trace(plan, t, [gpu_bundle(api, dirs, 16, 16, chis, a, b)], obs,
+                        kappa=kap, kappa_comp=comp, debug=True)
+        ref = oracle.trace_uniform(n, box, obs, dirs, chis, a, b, phi=phi.astype(np.float64))
+        assert np.array_equal(hashes_u64(seg.hash), ref.hash)
+    ref_all = oracle.trace_uniform(n, box, obs, dirs, chis, chis, 0.0, phi=phi.astype(np.float64))
+    k1 = one.kappa.cpu().numpy().astype(np.float64)
+    ks = kap.cpu().numpy().astype(np.float64)
+    if prec == "fp64":
+        np.testing.assert_allclose(ks, k1, rtol=0, atol=1e-12 * np.abs(k1).max())
+    else:
+        ok, worst = kappa_tolerance_ok(ks, ref_all.kappa)
+        assert ok, worst
+
+
+def test_open_boundary_cubic_and_domain_status(api, oracle, plan):
+    """Open grid (padded): cubic potential parity with the oracle, and rays
+    that leave [2, n-3]^3 report RR_RAY_OUT_OF_DOMAIN like the oracle."""
+    n = 28
+    idx = np.arange(n) + 0.5
+    z, y, x = np.meshgrid(idx, idx, idx, indexing="ij")
+    phi = 0.3 * x * x - 0.2 * x * y + 0.01 * x * y * z + 0.05 * z ** 3 / 6
+    g = gpu_grid(api, phi, float(n), boundary="open")
+    t = api.TidalTensor(g, "fp64").build()
+    fov = math.radians(60.0)
+    dirs = I.fov_directions((0.0, 0.0, 1.0), fov, fov, 8, 8)
+    obs = (14.0, 14.0, 3.0)
+    out = api.trace(plan, t, [gpu_bundle(api, dirs, 8, 8, 40.0, 24.0, 0.5)], obs, debug=True)
+    ref = oracle.trace_uniform(n, float(n), obs, dirs, 40.0, 24.0, 0.5, phi=phi,
+                               open_boundary=True)
+    st = out.status.cpu().numpy()
+    assert np.array_equal(st, ref.status)
+    assert (st == 1).any() and (st == 0).any()
+    assert np.array_equal(out.count.cpu().numpy(), ref.ncross)
+    assert np.array_equal(hashes_u64(out.hash), ref.hash)
+    np.testing.assert_allclose(out.kappa.cpu().numpy(), ref.kappa, rtol=0,
+                               atol=1e-11 * np.abs(ref.kappa).max())
+
+
+def test_max_crossings_status(api, plan):
+    n, box = 32, 64.0
+    phi, dirs = small_periodic_case(n=n, box=box, nx=8, ny=8)
+    g = gpu_grid(api, phi, box)
+    t = api.TidalTensor(g, "fp64").build()
+    out = api.trace(plan, t, [gpu_bundle(api, dirs, 8, 8, 90.0, 80.0, 0.0)], (0, 0, 0),
+                    max_crossings=7, debug=True)
+    assert np.all(out.status.cpu().numpy() == 2)
+    assert np.all(out.count.cpu().numpy() == 7)
+
+
+@pytest.mark.parametrize("quantity,q", [("gamma1", 1), ("gamma2", 2)])
+def test_shear_projections_match_oracle(api, oracle, plan, quantity, q):
+    n, box = 32, 64.0
+    phi, dirs = small_periodic_case(seed=7, n=n, box=box, nx=16, ny=8)
+    g = gpu_grid(api, phi, box)
+    t = api.TidalTensor(g, "fp64").build()
+    obs = (1.0, 2.0, 3.0)
+    out = api.trace(plan, t, [gpu_bundle(api, dirs, 16, 8, 90.0, 80.0, 0.0)], obs,
+                    quantity=quantity)
+    ref = oracle.trace_uniform(n, box, obs, dirs, 90.0, 80.0, 0.0, phi=phi, quantity=q)
+    np.testing.assert_allclose(out.kappa.cpu().numpy(), ref.kappa, rtol=0,
+                               atol=1e-11 * np.abs(ref.kappa).max())
+
+
+def test_persistent_queue_equals_direct_launch(api, plan):
+    """Persistent workgroups pulling tiles from the device queue give results
+    bitwise equal to one wavefront per tile (each ray is sequential)."""
+    n, box = 32, 64.0
+    phi, dirs = small_periodic_case(seed=8, n=n, box=box, nx=64, ny=40)
+    g = gpu_grid(api, phi.astype(np.float32), box)
+    t = api.TidalTensor(g, "fp32").build()
+    b = gpu_bundle(api, dirs, 64, 40, 90.0, 80.0, 0.0)
+    a = api.trace(plan, t, [b], (0, 0, 0), persistent=0, debug=True)
+    p = api.trace(plan, t, [b], (0, 0, 0), persistent=1, debug=True)
+    assert np.array_equal(a.kappa.cpu().numpy(), p.kappa.cpu().numpy())
+    assert np.array_equal(a.hash.cpu().numpy(), p.hash.cpu().numpy())
+
+
+def test_graph_capture_replays_match_eager(api, plan):
+    """A captured [tensor build -> trace] step replays correctly several
+    times, with eager work and synchronisation between replays."""
+    import torch
+    n, box = 32, 64.0
+    phi, dirs = small_periodic_case(seed=9, n=n, box=box, nx=16, ny=16)
+    g = gpu_grid(api, phi.astype(np.float32), box)
+    t = api.TidalTensor(g, "fp32")
+    b = gpu_bundle(api, dirs, 16, 16, 90.0, 80.0, 0.0)
+    kap = torch.zeros(256, dtype=torch.float32, device="cuda")
+    comp = torch.zeros(256, dtype=torch.float32, device="cuda")
+    st = torch.zeros(256, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t.build(g)
+        api.trace(plan, t, [b], (0, 0, 0), kappa=kap, kappa_comp=comp, status=st, persistent=1)
+        s.synchronize()
+        eager = kap.clone()
+        plan.graph_begin()
+        t.build(g)
+        api.trace(plan, t, [b], (0, 0, 0), kappa=kap, kappa_comp=comp, status=st, persistent=1)
+        plan.graph_end()
+    for rep in range(4):
+        kap.zero_()
+        comp.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            plan.graph_launch()
+        s.synchronize()
+        assert torch.equal(kap, eager), rep
+        _ = (kap * 2).sum().item()             # unrelated eager work between replays
