@@ -206,11 +206,19 @@ def cpu_baseline(phis, segs, dirs, chi_s, box, obs, n_sample, results):
     tv = O.vertex_tensor(phi)
     t_tensor = time.perf_counter() - t0
     rng = np.random.default_rng(12345)
-    sel = np.sort(rng.choice(dirs.shape[0], size=min(n_sample, dirs.shape[0]), replace=False))
+    perm = rng.permutation(dirs.shape[0])
+    # pilot run, then size the sample to about 15 s of oracle work
+    pilot = np.sort(perm[:min(n_sample, dirs.shape[0])])
+    t0 = time.perf_counter()
+    rp = O.trace_uniform(n, box, obs, dirs[pilot], chi_s, hi, lo, tv=tv, threads=cores)
+    tp = max(time.perf_counter() - t0, 1e-3)
+    want = int(len(pilot) * min(15.0 / tp, 1e6))
+    sel = np.sort(perm[:max(len(pilot), min(want, dirs.shape[0]))])
     t0 = time.perf_counter()
     r = O.trace_uniform(n, box, obs, dirs[sel], chi_s, hi, lo, tv=tv, threads=cores)
     t_trace = time.perf_counter() - t0
     cross = int(r.ncross.sum())
+    del rp
     log(f"oracle: tensor {t_tensor:.1f}s, {len(sel)} rays / {cross} crossings in {t_trace:.1f}s")
     # GPU FP32 segment result for the same rays and segment (parity sample)
     from paper_1601_02012_amd import api
