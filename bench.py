@@ -49,6 +49,9 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=8192)
     ap.add_argument("--profile-steps", action="store_true",
                     help="short run for profilers: skip the CPU baseline and the FP64 leg")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB device-to-device (a plain "
+                         "copy kernel that calibrates the profiler's byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -140,6 +143,16 @@ def main():
         t.close()
         del kap, comp, st
         torch.cuda.empty_cache()
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib * (1 << 20)
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB x 3")
+        del src, dst
 
     r32 = results["fp32"]
     value = r32["cross"] / (r32["step_ms"] * 1e-3)

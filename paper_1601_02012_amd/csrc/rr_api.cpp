@@ -141,7 +141,7 @@ rr_status rr_tensor_create(const rr_field_desc* f, rr_precision p, rr_tensor* ou
   t->box = f->box_size;
   if (f->kind == RR_GRID_UNIFORM) {
     const int64_t nv = (int64_t)f->n_base * f->n_base * f->n_base;
-    t->record_bytes = p == RR_PREC_FP32_KAHAN ? 32 : 48;
+    t->record_bytes = p == RR_PREC_FP32_KAHAN ? 24 : 48;
     t->n_records = nv;
     hipError_t e = hipMalloc(&t->data, (size_t)nv * t->record_bytes);
     if (e != hipSuccess) return fail(RR_ERR_OOM, "vertex tensor: %s", hipGetErrorString(e));

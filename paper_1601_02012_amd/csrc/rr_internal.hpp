@@ -43,13 +43,13 @@ struct TraceArgs {
   unsigned long long* queue;
 };
 
-// Uniform vertex tensor record: FP32 -> 8 floats (6 used, 32 B, two 16-byte
-// loads); FP64 -> 6 doubles (48 B, three 16-byte loads).
+// Uniform vertex tensor record: 6 components, FP32 (24 B, three 8-byte
+// accesses) or FP64 (48 B, three 16-byte accesses).
 template <typename Real>
 struct VertexRecord;
 template <>
 struct VertexRecord<float> {
-  static constexpr int kWords = 8;
+  static constexpr int kWords = 6;
 };
 template <>
 struct VertexRecord<double> {

@@ -20,60 +20,72 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 }
 
 template <typename R>
-__device__ __forceinline__ void load_vertex(const R* __restrict__ tv, int64_t v, R* t);
+__device__ __forceinline__ void load_vertex(const R* __restrict__ tv, uint64_t v, R* t);
 
 template <>
-__device__ __forceinline__ void load_vertex<float>(const float* __restrict__ tv, int64_t v,
+__device__ __forceinline__ void load_vertex<float>(const float* __restrict__ tv, uint64_t v,
                                                    float* t) {
-  const float4* p = reinterpret_cast<const float4*>(tv + v * 8);
-  const float4 a = p[0], b = p[1];
-  t[0] = a.x; t[1] = a.y; t[2] = a.z; t[3] = a.w; t[4] = b.x; t[5] = b.y;
+  const float2* p = reinterpret_cast<const float2*>(tv + v * 6);
+  const float2 a = p[0], b = p[1], c = p[2];
+  t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y; t[4] = c.x; t[5] = c.y;
 }
 template <>
-__device__ __forceinline__ void load_vertex<double>(const double* __restrict__ tv, int64_t v,
+__device__ __forceinline__ void load_vertex<double>(const double* __restrict__ tv, uint64_t v,
                                                     double* t) {
   const double2* p = reinterpret_cast<const double2*>(tv + v * 6);
   const double2 a = p[0], b = p[1], c = p[2];
   t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y; t[4] = c.x; t[5] = c.y;
 }
 
-template <typename R, bool kDebug>
+// One ray.  Per axis the lane keeps, in FP64, the coordinate of the exit
+// plane, its crossing parameter and the local-coordinate offset o~ - m; the
+// cell's wrapped indices are kept as integer offsets into the vertex array, so
+// a crossing costs no integer division and no int->float conversion.
+template <typename R, bool kDebug, typename Idx>
 __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const DevBundle& B,
                           int64_t ray) {
   const int64_t out = B.ray_offset + ray;
-  const double dx = B.dir[3 * ray + 0], dy = B.dir[3 * ray + 1], dz = B.dir[3 * ray + 2];
-  const double d[3] = {dx, dy, dz};
+  const double d[3] = {B.dir[3 * ray + 0], B.dir[3 * ray + 1], B.dir[3 * ray + 2]};
   // Only unit directions are traced: that bounds the number of crossings by
   // the chi window validated on the host, so every lane terminates.
-  const double nrm2 = dx * dx + dy * dy + dz * dz;
+  const double nrm2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
   if (!(fabs(nrm2 - 1.0) <= 1e-9)) {
     if (a.status) a.status[out] = RR_RAY_BAD_DIRECTION;
     return;
   }
-  double r[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) r[k] = (d[k] != 0.0) ? 1.0 / d[k] : 0.0;
-
   double Pd[6];
-  projection(a.quantity, dx, dy, dz, Pd);
+  projection(a.quantity, d[0], d[1], d[2], Pd);
   R P[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) P[c] = (R)Pd[c];
 
   const int n = a.n;
+  const Idx nI = (Idx)n, nnI = (Idx)n * (Idx)n;
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
-  int m[3];
-  double te[3];
+  double r[3], pe[3], te[3], cpos[3], sgn[3];
+  int m[3], w[3];
+  Idx off0[3], off1[3];           // wrapped offsets of the cell's lower / upper vertex layer
+  const Idx stride[3] = {(Idx)1, nI, nnI};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
+    r[k] = (d[k] != 0.0) ? 1.0 / d[k] : 0.0;
     m[k] = start_slab(a.o[k], d[k], r[k], chiA, 1.0);
-    te[k] = texit_of(m[k], a.o[k], d[k], r[k], 1.0);
+    sgn[k] = d[k] > 0.0 ? -1.0 : 1.0;            // step of m along the march
+    pe[k] = (double)(d[k] > 0.0 ? m[k] : m[k] + 1);
+    te[k] = d[k] != 0.0 ? tplane(pe[k], a.o[k], r[k]) : -__builtin_inf();
+    cpos[k] = a.o[k] - (double)m[k];
+    int ww = m[k] % n;
+    w[k] = ww < 0 ? ww + n : ww;
+    off0[k] = (Idx)w[k] * stride[k];
+    off1[k] = (Idx)(w[k] + 1 == n ? 0 : w[k] + 1) * stride[k];
   }
+  R uA[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) uA[k] = (R)fma(chiA, d[k], cpos[k]);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
-  // accumulators continue the caller's running sums
   R sum;
   float comp = 0.0f;
   if constexpr (sizeof(R) == 4) {
@@ -86,7 +98,6 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   int64_t count = 0;
   int32_t st = RR_RAY_OK;
   const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
-  const int64_t nn = (int64_t)n * n;
 
   for (;;) {
     if (a.open && (m[0] < 2 || m[1] < 2 || m[2] < 2 || m[0] > n - 3 || m[1] > n - 3 ||
@@ -100,44 +111,36 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     }
     // exit point: chi_B = max(chi_lo, t_exit,x, t_exit,y, t_exit,z), ties keep the earlier
     double chiB = lo;
-    if (te[0] > chiB) chiB = te[0];
-    if (te[1] > chiB) chiB = te[1];
-    if (te[2] > chiB) chiB = te[2];
+    chiB = te[0] > chiB ? te[0] : chiB;
+    chiB = te[1] > chiB ? te[1] : chiB;
+    chiB = te[2] > chiB ? te[2] : chiB;
+    bool stepped[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
 
-    // eight corners of cell m
-    int x0, y0, z0, x1, y1, z1;
-    if (a.open) {
-      x0 = m[0]; y0 = m[1]; z0 = m[2];
-      x1 = x0 + 1; y1 = y0 + 1; z1 = z0 + 1;
-    } else {
-      x0 = wrapi(m[0], n); y0 = wrapi(m[1], n); z0 = wrapi(m[2], n);
-      x1 = (x0 + 1 == n) ? 0 : x0 + 1;
-      y1 = (y0 + 1 == n) ? 0 : y0 + 1;
-      z1 = (z0 + 1 == n) ? 0 : z0 + 1;
-    }
-    const int64_t zo0 = (int64_t)z0 * nn, zo1 = (int64_t)z1 * nn;
-    const int64_t yo0 = (int64_t)y0 * n, yo1 = (int64_t)y1 * n;
+    // the eight corners (v = ix + 2 iy + 4 iz), projected on the ray's P
     R q[8];
     {
-      const int64_t vid[8] = {zo0 + yo0 + x0, zo0 + yo0 + x1, zo0 + yo1 + x0, zo0 + yo1 + x1,
-                              zo1 + yo0 + x0, zo1 + yo0 + x1, zo1 + yo1 + x0, zo1 + yo1 + x1};
+      const Idx zy00 = off0[2] + off0[1], zy01 = off0[2] + off1[1];
+      const Idx zy10 = off1[2] + off0[1], zy11 = off1[2] + off1[1];
+      const Idx vid[8] = {zy00 + off0[0], zy00 + off1[0], zy01 + off0[0], zy01 + off1[0],
+                          zy10 + off0[0], zy10 + off1[0], zy11 + off0[0], zy11 + off1[0]};
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         R t[6];
-        load_vertex<R>(tv, vid[v], t);
+        load_vertex<R>(tv, (uint64_t)vid[v], t);
         R acc = P[0] * t[0];
 #pragma unroll
         for (int c = 1; c < 6; ++c) acc = fma(P[c], t[c], acc);
         q[v] = acc;
       }
     }
-    // local coordinates of the entry and exit points (FP64, then R)
-    R uA[3], uB[3];
+    // local coordinates of the exit point; exact on the crossed faces
+    R uB[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double base = a.o[k] - (double)m[k];
-      uA[k] = (R)fma(chiA, d[k], base);
-      uB[k] = (R)fma(chiB, d[k], base);
+      const R face = d[k] > 0.0 ? (R)0 : (R)1;
+      uB[k] = stepped[k] ? face : (R)fma(chiB, d[k], cpos[k]);
     }
     const R L = (R)(chiA - chiB);
     const R ic = cell_integral<R>(q, uA, uB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
@@ -147,7 +150,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
       sum += ic;
     }
     if constexpr (kDebug) {
-      const int64_t cell = zo0 + yo0 + x0;
+      const int64_t cell = (int64_t)(off0[2] + off0[1] + off0[0]);
       if (a.hash) hv = fnv_piece(hv, cell, chiA, chiB);
       if (a.log && count < a.log_stride) {
         LogRecord* L0 = reinterpret_cast<LogRecord*>(a.log) + out * a.log_stride + count;
@@ -158,12 +161,23 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     }
     ++count;
     if (chiB == lo) break;
-    // step every axis whose exit plane is at chi_B
+    // step every axis whose exit plane is at chi_B; the entry point of the
+    // next cell is the exit point of this one
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      if (te[k] == chiB) {
-        m[k] += (d[k] > 0.0) ? -1 : 1;
-        te[k] = texit_of(m[k], a.o[k], d[k], r[k], 1.0);
+      uA[k] = uB[k];
+      if (stepped[k]) {
+        pe[k] += sgn[k];
+        te[k] = tplane(pe[k], a.o[k], r[k]);
+        cpos[k] -= sgn[k];
+        uA[k] = (R)1 - uB[k];
+        const int s = d[k] > 0.0 ? -1 : 1;
+        m[k] += s;
+        int ww = w[k] + s;
+        ww = ww < 0 ? ww + n : (ww >= n ? ww - n : ww);
+        w[k] = ww;
+        off0[k] = (Idx)ww * stride[k];
+        off1[k] = (Idx)(ww + 1 == n ? 0 : ww + 1) * stride[k];
       }
     }
     chiA = chiB;
@@ -182,7 +196,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   }
 }
 
-template <typename R, bool kDebug>
+template <typename R, bool kDebug, typename Idx>
 __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -190,12 +204,12 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug>(tv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Idx>(tv, a, B, (int64_t)iy * B.nx + ix);
 }
 
 // One wavefront per tile.  Workgroups are dealt round-robin to the 8 XCDs;
 // remap so that XCD x gets the x-th contiguous slice of tiles.
-template <typename R, bool kDebug>
+template <typename R, bool kDebug, typename Idx>
 __global__ __launch_bounds__(256) void march_uniform_kernel(const R* __restrict__ tv,
                                                             TraceArgs a) {
   const int lane = threadIdx.x & 63;
@@ -207,12 +221,12 @@ __global__ __launch_bounds__(256) void march_uniform_kernel(const R* __restrict_
   const int64_t vblk = xcd * per + slot;
   const int64_t tile = vblk * (blockDim.x >> 6) + wave;
   if (tile >= a.n_tiles) return;
-  run_tile<R, kDebug>(tv, a, tile, lane);
+  run_tile<R, kDebug, Idx>(tv, a, tile, lane);
 }
 
 // Persistent workgroups: every wavefront pulls tiles from a device counter
 // until the queue is drained (every wave reaches the exit test).
-template <typename R, bool kDebug>
+template <typename R, bool kDebug, typename Idx>
 __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restrict__ tv,
                                                                 TraceArgs a) {
   const int lane = threadIdx.x & 63;
@@ -221,37 +235,40 @@ __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restr
     if (lane == 0) t = atomicAdd(a.queue, 1ull);
     t = __shfl(t, 0, 64);
     if ((int64_t)t >= a.n_tiles) break;
-    run_tile<R, kDebug>(tv, a, (int64_t)t, lane);
+    run_tile<R, kDebug, Idx>(tv, a, (int64_t)t, lane);
   }
 }
 
 __global__ void queue_reset_kernel(unsigned long long* q) { *q = 0ull; }
 
-template <typename R>
-hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
-                  hipStream_t s) {
-  const bool dbg = a.hash || a.log || a.count;
+template <typename R, bool kDebug, typename Idx>
+hipError_t launch3(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
+                   hipStream_t s) {
   const int wpb = block / 64;
   if (persistent) {
     const int blocks = (grid_waves + wpb - 1) / wpb;
-    if (dbg)
-      hipLaunchKernelGGL((march_uniform_persistent<R, true>), dim3(blocks), dim3(block), 0, s,
-                         (const R*)tv, a);
-    else
-      hipLaunchKernelGGL((march_uniform_persistent<R, false>), dim3(blocks), dim3(block), 0, s,
-                         (const R*)tv, a);
+    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Idx>), dim3(blocks), dim3(block), 0, s,
+                       (const R*)tv, a);
   } else {
     int64_t blocks = (a.n_tiles + wpb - 1) / wpb;
     if (blocks == 0) return hipSuccess;
     blocks = (blocks + 7) / 8 * 8;   // the XCD remap is a bijection on multiples of 8
-    if (dbg)
-      hipLaunchKernelGGL((march_uniform_kernel<R, true>), dim3((unsigned)blocks), dim3(block), 0,
-                         s, (const R*)tv, a);
-    else
-      hipLaunchKernelGGL((march_uniform_kernel<R, false>), dim3((unsigned)blocks), dim3(block), 0,
-                         s, (const R*)tv, a);
+    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Idx>), dim3((unsigned)blocks), dim3(block),
+                       0, s, (const R*)tv, a);
   }
   return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
+                  hipStream_t s) {
+  const bool dbg = a.hash || a.log || a.count;
+  const bool small = (int64_t)a.n * a.n * a.n < (1ll << 32);
+  if (dbg)
+    return small ? launch3<R, true, uint32_t>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, true, uint64_t>(tv, a, persistent, block, grid_waves, s);
+  return small ? launch3<R, false, uint32_t>(tv, a, persistent, block, grid_waves, s)
+               : launch3<R, false, uint64_t>(tv, a, persistent, block, grid_waves, s);
 }
 
 }  // namespace

@@ -14,8 +14,4 @@ hipError_t OctreeTensor::march(const TraceArgs&, int, int, hipStream_t) {
 }
 OctreeTensor::~OctreeTensor() {}
 
-hipError_t launch_adjoint_uniform(const TraceArgs&, const float*, float*, float*, hipStream_t) {
-  return hipErrorNotSupported;
-}
-
 }  // namespace rr

@@ -1,140 +1,180 @@
 // rr_tensor_uniform.hip -- tidal tensor at cell centres (Eq. tidalexample) fused
 // with its interpolation to cell vertices (Sec. III F, regular vertices).
 //
-// One workgroup builds a TX x TY x TZ block of vertices.  It stages the
-// potential of the block plus a two-cell halo in LDS, evaluates the centre
-// tensor of the (TX+1)(TY+1)(TZ+1) cells that touch those vertices into LDS,
-// and writes every vertex as the mean of its eight cells.  Vertex (i,j,k) is
-// the lower corner of cell (i,j,k).  Second differences are formed as
-// differences of neighbour differences, which are exact in floating point
-// for neighbours within a factor two of each other (Sterbenz).
+// Vertex (i,j,k) is the lower corner of cell (i,j,k) and takes the mean of the
+// centre tensors of cells {i-1,i} x {j-1,j} x {k-1,k}.  Summing the centre
+// stencils over those eight cells factorises per axis into
+//   second difference summed over two cells: S f(i) = (f(i+1) - f(i)) - (f(i-1) - f(i-2))
+//   first difference summed over two cells:  D f(i) = (f(i+1) - f(i-1)) + (f(i) - f(i-2))
+//   plain sum over the two cells:            B f(i) = f(i-1) + f(i)
+// so that   T_xx = (1/8) S_x B_y B_z Phi,   T_xy = (1/32) D_x D_y B_z Phi, ...
+// Differences are always taken first on the raw potential (exact for
+// neighbours within a factor two, Sterbenz), sums afterwards.
+//
+// Layout of the work: a workgroup owns a 64 x 4 column of vertices in x-y and
+// marches along z.  Each step stages one potential plane (plus a two-cell
+// halo) in LDS; every thread reads its 4 x 4 patch of that plane once and
+// keeps the per-plane partial stencils of the last four planes in registers,
+// so each potential value is read from HBM about once and each vertex costs
+// 16 LDS reads and ~80 arithmetic operations.
 #include "rr_internal.hpp"
 
 namespace rr {
 namespace {
 
-template <typename Acc>
-struct TileShape;
-template <>
-struct TileShape<float> {  // 64x4x4 vertices: LDS 3283*4 + 1625*24 = 52 KB
-  static constexpr int TX = 64, TY = 4, TZ = 4;
-};
-template <>
-struct TileShape<double> {  // 32x4x4 vertices: LDS 2695... see below, < 64 KB
-  static constexpr int TX = 32, TY = 4, TZ = 4;
-};
+constexpr int TX = 64, TY = 4;          // vertices per workgroup in x, y
+constexpr int PX = TX + 3, PY = TY + 3; // staged plane: halo 2 below, 1 above
+constexpr int KZ = 32;                  // vertices per workgroup along z
 
 __device__ inline int wrapi(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
 
-template <typename In, typename Acc, typename Out>
-__global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __restrict__ phi,
-                                                                    Out* __restrict__ tv, int n,
-                                                                    int open, int ntx, int nty) {
-  constexpr int TX = TileShape<Acc>::TX, TY = TileShape<Acc>::TY, TZ = TileShape<Acc>::TZ;
-  constexpr int PX = TX + 3, PY = TY + 3, PZ = TZ + 3;   // potential tile (halo 2 below, 1 above)
-  constexpr int CX = TX + 1, CY = TY + 1, CZ = TZ + 1;   // centre-tensor tile
-  constexpr int RW = VertexRecord<Out>::kWords;
-  __shared__ Acc sphi[PZ * PY * PX];
-  __shared__ Acc sten[6][CZ * CY * CX];
+template <typename Out>
+__device__ inline void store_vertex(Out* dst, const Out* rec);
+template <>
+__device__ inline void store_vertex<float>(float* dst, const float* r) {
+  float2* d2 = reinterpret_cast<float2*>(dst);
+  d2[0] = make_float2(r[0], r[1]);
+  d2[1] = make_float2(r[2], r[3]);
+  d2[2] = make_float2(r[4], r[5]);
+}
+template <>
+__device__ inline void store_vertex<double>(double* dst, const double* r) {
+  double2* d2 = reinterpret_cast<double2*>(dst);
+  d2[0] = make_double2(r[0], r[1]);
+  d2[1] = make_double2(r[2], r[3]);
+  d2[2] = make_double2(r[4], r[5]);
+}
 
-  // workgroup -> tile (x fastest)
+template <typename In, typename Acc>
+__global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __restrict__ phi,
+                                                                    Acc* __restrict__ tv, int n,
+                                                                    int open, int ntx, int nty) {
+  constexpr int RW = VertexRecord<Acc>::kWords;
+  __shared__ Acc plane[2][PY * PX];
+
   const int b = blockIdx.x;
   const int bx = b % ntx;
   const int by = (b / ntx) % nty;
   const int bz = b / (ntx * nty);
-  const int i0 = bx * TX, j0 = by * TY, k0 = bz * TZ;
+  const int i0 = bx * TX, j0 = by * TY, k0 = bz * KZ;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = i0 + tx, j = j0 + ty;
+  const int64_t nn = (int64_t)n * n;
 
-  // stage 0: potential with halo, x fastest for coalescing
-  for (int e = threadIdx.x; e < PZ * PY * PX; e += blockDim.x) {
-    const int x = e % PX, y = (e / PX) % PY, z = e / (PX * PY);
-    int gi = i0 - 2 + x, gj = j0 - 2 + y, gk = k0 - 2 + z;
-    Acc v;
-    if (open) {
-      const bool in = gi >= 0 && gj >= 0 && gk >= 0 && gi < n && gj < n && gk < n;
-      v = in ? (Acc)phi[((int64_t)gk * n + gj) * n + gi] : (Acc)0;
-    } else {
-      gi = wrapi(gi, n);
-      gj = wrapi(gj, n);
-      gk = wrapi(gk, n);
-      v = (Acc)phi[((int64_t)gk * n + gj) * n + gi];
-    }
-    sphi[e] = v;
+  // per-plane partial stencils, history over planes (index 0 = oldest)
+  Acc XX[2], YY[2], XY[2];     // planes k-1, k
+  Acc Z[4][4];                 // raw Phi of the 2x2 column box, planes k-2..k+1
+  Acc DX[4][2], DY[4][2];      // D_x on rows j-1, j and D_y on columns i-1, i, planes k-2..k+1
+
+  // staging: each thread copies at most two elements of every plane; their
+  // (wrapped) x-y offsets are fixed for the whole march
+  constexpr int kStage = (PX * PY + 255) / 256;
+  int soff[kStage];
+  bool sin_[kStage], sact[kStage];
+#pragma unroll
+  for (int u = 0; u < kStage; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    sact[u] = e < PX * PY;
+    const int lx = e % PX, ly = e / PX;
+    int gx = i0 - 2 + lx, gy = j0 - 2 + ly;
+    sin_[u] = gx >= 0 && gy >= 0 && gx < n && gy < n;
+    if (gx < 0) gx += n; else if (gx >= n) gx -= n;
+    if (gy < 0) gy += n; else if (gy >= n) gy -= n;
+    soff[u] = gy * n + gx;
   }
-  __syncthreads();
 
-  // stage 1: centre tensor of cells i0-1 .. i0+TX-1 (etc.)
-  for (int e = threadIdx.x; e < CZ * CY * CX; e += blockDim.x) {
-    const int x = e % CX, y = (e / CX) % CY, z = e / (CX * CY);
-    // cell (i0-1+x) sits at potential-tile index x+1
-    const int px = x + 1, py = y + 1, pz = z + 1;
-#define P(dx, dy, dz) sphi[((pz + (dz)) * PY + (py + (dy))) * PX + (px + (dx))]
-    const Acc c = P(0, 0, 0);
-    Acc txx = (P(1, 0, 0) - c) - (c - P(-1, 0, 0));
-    Acc tyy = (P(0, 1, 0) - c) - (c - P(0, -1, 0));
-    Acc tzz = (P(0, 0, 1) - c) - (c - P(0, 0, -1));
-    Acc txy = ((P(1, 1, 0) - P(1, -1, 0)) - (P(-1, 1, 0) - P(-1, -1, 0))) * (Acc)0.25;
-    Acc txz = ((P(1, 0, 1) - P(1, 0, -1)) - (P(-1, 0, 1) - P(-1, 0, -1))) * (Acc)0.25;
-    Acc tyz = ((P(0, 1, 1) - P(0, 1, -1)) - (P(0, -1, 1) - P(0, -1, -1))) * (Acc)0.25;
-#undef P
-    if (open) {
-      const int gi = i0 - 1 + x, gj = j0 - 1 + y, gk = k0 - 1 + z;
-      const bool in = gi >= 1 && gj >= 1 && gk >= 1 && gi <= n - 2 && gj <= n - 2 && gk <= n - 2;
-      if (!in) {
-        const Acc nan = (Acc)__builtin_nan("");
-        txx = tyy = tzz = txy = txz = tyz = nan;
+  const int k_end = min(k0 + KZ, n);
+  int slot = 0;
+  int gz = k0 - 2;
+  if (gz < 0) gz += n;
+  for (int p = k0 - 2; p <= k_end; ++p, slot ^= 1) {
+    // stage plane p (x fastest, wrapped or zero-padded)
+    Acc* pl = plane[slot];
+    const bool zin = p >= 0 && p < n;
+    const In* src = phi + (int64_t)gz * nn;
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      if (!sact[u]) continue;
+      Acc v;
+      if (open)
+        v = (sin_[u] && zin) ? (Acc)src[soff[u]] : (Acc)0;
+      else
+        v = (Acc)src[soff[u]];
+      pl[threadIdx.x + 256 * u] = v;
+    }
+    if (++gz == n) gz = 0;
+    __syncthreads();
+    // 4x4 patch: rows y = j-2..j+1, columns x = i-2..i+1
+    Acc q[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[r][c] = pl[(ty + r) * PX + (tx + c)];
+
+    Acc dx[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dx[r] = (q[r][3] - q[r][1]) + (q[r][2] - q[r][0]);
+    const Acc sxx = ((q[1][3] - q[1][2]) - (q[1][1] - q[1][0])) +
+                    ((q[2][3] - q[2][2]) - (q[2][1] - q[2][0]));
+    const Acc syy = ((q[3][1] - q[2][1]) - (q[1][1] - q[0][1])) +
+                    ((q[3][2] - q[2][2]) - (q[1][2] - q[0][2]));
+    const Acc dxy = (dx[3] - dx[1]) + (dx[2] - dx[0]);
+    const Acc dy1 = (q[3][1] - q[1][1]) + (q[2][1] - q[0][1]);
+    const Acc dy2 = (q[3][2] - q[1][2]) + (q[2][2] - q[0][2]);
+
+    // shift the z histories so that Z/DX/DY[0..3] hold planes p-3..p
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Z[h][c] = Z[h + 1][c];
+      DX[h][0] = DX[h + 1][0]; DX[h][1] = DX[h + 1][1];
+      DY[h][0] = DY[h + 1][0]; DY[h][1] = DY[h + 1][1];
+    }
+    Z[3][0] = q[1][1]; Z[3][1] = q[1][2]; Z[3][2] = q[2][1]; Z[3][3] = q[2][2];
+    DX[3][0] = dx[1]; DX[3][1] = dx[2];
+    DY[3][0] = dy1; DY[3][1] = dy2;
+
+    if (p >= k0 + 1 && i < n && j < n) {
+      // vertex k = p - 1: Z/DX/DY[0..3] are planes k-2..k+1; XX/YY/XY[0..1] are k-1, k
+      const int k = p - 1;
+      Acc rec[6];
+      rec[0] = (XX[0] + XX[1]) * (Acc)0.125;
+      rec[1] = (YY[0] + YY[1]) * (Acc)0.125;
+      Acc zz = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) zz += (Z[3][c] - Z[2][c]) - (Z[1][c] - Z[0][c]);
+      rec[2] = zz * (Acc)0.125;
+      rec[3] = (XY[0] + XY[1]) * (Acc)0.03125;
+      Acc xz = 0, yz = 0;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        xz += (DX[3][c] - DX[1][c]) + (DX[2][c] - DX[0][c]);
+        yz += (DY[3][c] - DY[1][c]) + (DY[2][c] - DY[0][c]);
       }
-    }
-    sten[0][e] = txx;
-    sten[1][e] = tyy;
-    sten[2][e] = tzz;
-    sten[3][e] = txy;
-    sten[4][e] = txz;
-    sten[5][e] = tyz;
-  }
-  __syncthreads();
-
-  // stage 2: vertices, mean of the eight cells around each
-  for (int e = threadIdx.x; e < TZ * TY * TX; e += blockDim.x) {
-    const int x = e % TX, y = (e / TX) % TY, z = e / (TX * TY);
-    const int gi = i0 + x, gj = j0 + y, gk = k0 + z;
-    if (gi >= n || gj >= n || gk >= n) continue;
-    // vertex (gi,gj,gk) touches cells gi-1, gi -> centre-tile x, x+1
-    Out rec[RW];
+      rec[4] = xz * (Acc)0.03125;
+      rec[5] = yz * (Acc)0.03125;
+      if (open && (i < 2 || j < 2 || k < 2 || i > n - 2 || j > n - 2 || k > n - 2)) {
+        const Acc nan = (Acc)__builtin_nan("");
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const Acc* s = sten[c];
-#define C(dx, dy, dz) s[((z + (dz)) * CY + (y + (dy))) * CX + (x + (dx))]
-      const Acc s0 = (C(0, 0, 0) + C(1, 0, 0)) + (C(0, 1, 0) + C(1, 1, 0));
-      const Acc s1 = (C(0, 0, 1) + C(1, 0, 1)) + (C(0, 1, 1) + C(1, 1, 1));
-#undef C
-      rec[c] = (Out)((s0 + s1) * (Acc)0.125);
+        for (int c = 0; c < 6; ++c) rec[c] = nan;
+      }
+      store_vertex<Acc>(tv + ((int64_t)k * nn + (int64_t)j * n + i) * RW, rec);
     }
-#pragma unroll
-    for (int c = 6; c < RW; ++c) rec[c] = (Out)0;
-    Out* dst = tv + (((int64_t)gk * n + gj) * n + gi) * RW;
-    if constexpr (RW == 8) {
-      float4* d4 = reinterpret_cast<float4*>(dst);
-      d4[0] = make_float4(rec[0], rec[1], rec[2], rec[3]);
-      d4[1] = make_float4(rec[4], rec[5], rec[6], rec[7]);
-    } else {
-      double2* d2 = reinterpret_cast<double2*>(dst);
-      d2[0] = make_double2(rec[0], rec[1]);
-      d2[1] = make_double2(rec[2], rec[3]);
-      d2[2] = make_double2(rec[4], rec[5]);
-    }
+    // XX/YY/XY hold planes (p-2, p-1) during step p; push plane p
+    XX[0] = XX[1]; YY[0] = YY[1]; XY[0] = XY[1];
+    XX[1] = sxx; YY[1] = syy; XY[1] = dxy;
   }
 }
 
-template <typename In, typename Acc, typename Out>
+template <typename In, typename Acc>
 hipError_t launch_vt(int n, int open, const void* phi, void* tv, hipStream_t s) {
-  constexpr int TX = TileShape<Acc>::TX, TY = TileShape<Acc>::TY, TZ = TileShape<Acc>::TZ;
-  const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY, ntz = (n + TZ - 1) / TZ;
+  const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY, ntz = (n + KZ - 1) / KZ;
   const int64_t blocks = (int64_t)ntx * nty * ntz;
-  hipLaunchKernelGGL((vertex_tensor_uniform_kernel<In, Acc, Out>), dim3((unsigned)blocks),
-                     dim3(256), 0, s, (const In*)phi, (Out*)tv, n, open, ntx, nty);
+  hipLaunchKernelGGL((vertex_tensor_uniform_kernel<In, Acc>), dim3((unsigned)blocks), dim3(256),
+                     0, s, (const In*)phi, (Acc*)tv, n, open, ntx, nty);
   return hipGetLastError();
 }
 
@@ -143,11 +183,11 @@ hipError_t launch_vt(int n, int open, const void* phi, void* tv, hipStream_t s) 
 hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int open,
                                         const void* phi, void* tv, hipStream_t s) {
   if (precision == RR_PREC_FP32_KAHAN) {
-    if (dtype == RR_F32) return launch_vt<float, float, float>(n, open, phi, tv, s);
-    return launch_vt<double, float, float>(n, open, phi, tv, s);
+    if (dtype == RR_F32) return launch_vt<float, float>(n, open, phi, tv, s);
+    return launch_vt<double, float>(n, open, phi, tv, s);
   }
-  if (dtype == RR_F32) return launch_vt<float, double, double>(n, open, phi, tv, s);
-  return launch_vt<double, double, double>(n, open, phi, tv, s);
+  if (dtype == RR_F32) return launch_vt<float, double>(n, open, phi, tv, s);
+  return launch_vt<double, double>(n, open, phi, tv, s);
 }
 
 }  // namespace rr
