@@ -1,0 +1,580 @@
+// rr_octree.hip -- tidal tensor and ray march on a 2:1-balanced AMR octree.
+//
+// Cells: base cells 0..n^3-1 ([z][y][x]), then oct k owns cells
+// n^3 + 8k + (ix + 2 iy + 4 iz); octs are breadth first, so every level is a
+// contiguous range of cells.  A level-l cell has size 2^-l base cells and
+// integer coordinates I at that level; locating a level-l position walks the
+// child_oct links down from its base cell (at most four loads).
+//
+// Build (Sec. IV C, Sec. III F):
+//  1. centre tensor, level by level: each component uses the level's own
+//     finite-difference stencil (Eq. tidalexample, h = 2^-l) when every
+//     stencil cell exists at level l; otherwise it is the trilinear
+//     interpolation (weights 3/4, 1/4 per axis) of the coarser level's
+//     component from the eight coarse centres around the cell centre;
+//  2. corner tensors of every leaf, level by level: a vertex whose incident
+//     leaves share one level takes their mean; a vertex in the middle of a
+//     coarse edge or face takes the mean of that coarse leaf's 2 or 4 corner
+//     values (already built, coarser level); any other vertex on a refinement
+//     boundary takes the mass-redistribution weights of Eqs. (alphac3d) and
+//     (alphaf3d), N_fv,j being the number of corners of fine leaf j that
+//     touch a coarse leaf.
+// March (Sec. III E): the uniform crossing rule on the current leaf's level;
+// past a face, a coarser neighbour is entered by halving the coordinates, a
+// refined one by descending to the child next to the crossed face (slab rule
+// on the other axes).
+#include "rr_octree.hpp"
+#include "rr_ray.hpp"
+
+namespace rr {
+namespace {
+
+struct Tree {
+  const int32_t* __restrict__ child;
+  const int4* __restrict__ info;   // per oct: x, y, z of child 0 (its level), level
+  int n;
+  int64_t nb;
+};
+
+__device__ __forceinline__ int64_t base_of(const Tree& T, int l, const int* I) {
+  int b[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int q = I[a] >> l;          // floor division by 2^l (arithmetic shift)
+    q %= T.n;
+    b[a] = q < 0 ? q + T.n : q;
+  }
+  return ((int64_t)b[2] * T.n + b[1]) * T.n + b[0];
+}
+
+// Cell at level l and coordinates I; if the tree stops above l, the covering
+// leaf.  Returns the level of the cell found.
+__device__ __forceinline__ int descend(const Tree& T, int l, const int* I, int64_t& cell) {
+  int64_t c = base_of(T, l, I);
+  for (int lev = 1; lev <= l; ++lev) {
+    const int k = T.child[c];
+    if (k < 0) {
+      cell = c;
+      return lev - 1;
+    }
+    const int s = l - lev;
+    const int ch = ((I[0] >> s) & 1) | (((I[1] >> s) & 1) << 1) | (((I[2] >> s) & 1) << 2);
+    c = T.nb + 8 * (int64_t)k + ch;
+  }
+  cell = c;
+  return l;
+}
+
+__device__ __forceinline__ void cell_coords(const Tree& T, int64_t c, int& level, int* I) {
+  if (c < T.nb) {
+    level = 0;
+    I[0] = (int)(c % T.n);
+    I[1] = (int)((c / T.n) % T.n);
+    I[2] = (int)(c / ((int64_t)T.n * T.n));
+    return;
+  }
+  const int64_t k = (c - T.nb) >> 3;
+  const int ch = (int)((c - T.nb) & 7);
+  const int4 inf = T.info[k];
+  level = inf.w;
+  I[0] = inf.x + (ch & 1);
+  I[1] = inf.y + ((ch >> 1) & 1);
+  I[2] = inf.z + ((ch >> 2) & 1);
+}
+
+// ----------------------------------------------------------- centre tensor --
+__constant__ int kMixed[3][4][3] = {
+    {{1, 1, 0}, {1, -1, 0}, {-1, 1, 0}, {-1, -1, 0}},   // xy: (++) (+-) (-+) (--)
+    {{1, 0, 1}, {1, 0, -1}, {-1, 0, 1}, {-1, 0, -1}},   // xz
+    {{0, 1, 1}, {0, 1, -1}, {0, -1, 1}, {0, -1, -1}},   // yz
+};
+
+template <typename In, typename Acc>
+__global__ __launch_bounds__(256) void centre_kernel(Tree T, const In* __restrict__ phi,
+                                                     Acc* __restrict__ tc, int l, int64_t begin,
+                                                     int64_t end) {
+  const int64_t c = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= end) return;
+  int lev, I[3];
+  cell_coords(T, c, lev, I);
+  const Acc inv_h2 = (Acc)(double)(1u << (2 * l));   // 1/h^2 with h = 2^-l
+  const Acc p0 = (Acc)phi[c];
+  Acc out[6];
+#pragma unroll
+  for (int comp = 0; comp < 6; ++comp) {
+    bool ok = true;
+    Acc v = 0;
+    if (comp < 3) {
+      int Jm[3] = {I[0], I[1], I[2]}, Jp[3] = {I[0], I[1], I[2]};
+      Jm[comp] -= 1;
+      Jp[comp] += 1;
+      int64_t cm, cp;
+      ok = descend(T, l, Jm, cm) == l && descend(T, l, Jp, cp) == l;
+      if (ok) v = (((Acc)phi[cp] - p0) - (p0 - (Acc)phi[cm])) * inv_h2;
+    } else {
+      Acc s[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int J[3] = {I[0] + kMixed[comp - 3][q][0], I[1] + kMixed[comp - 3][q][1],
+                          I[2] + kMixed[comp - 3][q][2]};
+        int64_t cc;
+        if (descend(T, l, J, cc) != l) {
+          ok = false;
+          s[q] = 0;
+        } else {
+          s[q] = (Acc)phi[cc];
+        }
+      }
+      if (ok) v = ((s[0] - s[1]) - (s[2] - s[3])) * ((Acc)0.25 * inv_h2);
+    }
+    if (!ok) {
+      // trilinear interpolation of the level-(l-1) component
+      int P[3], off[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        P[a] = I[a] >> 1;
+        off[a] = (I[a] & 1) ? 1 : -1;
+      }
+      Acc acc = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int J[3];
+        Acc w = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int nb_ = (q >> a) & 1;
+          J[a] = P[a] + (nb_ ? off[a] : 0);
+          w *= nb_ ? (Acc)0.25 : (Acc)0.75;
+        }
+        int64_t cc;
+        descend(T, l - 1, J, cc);
+        acc += w * tc[6 * cc + comp];
+      }
+      v = acc;
+    }
+    out[comp] = v;
+  }
+#pragma unroll
+  for (int comp = 0; comp < 6; ++comp) tc[6 * c + comp] = out[comp];
+}
+
+// ---------------------------------------------------------- corner tensors --
+// Leaf covering octant o (bit a set: above the vertex on axis a) around the
+// level-lv lattice point V.
+__device__ __forceinline__ int octant_leaf(const Tree& T, int lv, const int* V, int o,
+                                           int64_t& cell) {
+  const int J[3] = {V[0] - 1 + (o & 1), V[1] - 1 + ((o >> 1) & 1), V[2] - 1 + ((o >> 2) & 1)};
+  int lev = descend(T, lv, J, cell);
+  if (lev < lv) return lev;
+  const int ch = (1 - (o & 1)) | ((1 - ((o >> 1) & 1)) << 1) | ((1 - ((o >> 2) & 1)) << 2);
+  int k;
+  while ((k = T.child[cell]) >= 0) {
+    cell = T.nb + 8 * (int64_t)k + ch;
+    ++lev;
+  }
+  return lev;
+}
+
+template <typename Acc>
+__global__ __launch_bounds__(256) void corner_kernel(Tree T, const Acc* __restrict__ tc,
+                                                     Acc* __restrict__ cv, int l, int64_t begin,
+                                                     int64_t end) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = begin + (g >> 3);
+  const int v = (int)(g & 7);
+  if (c >= end) return;
+  Acc* out = cv + 48 * c + 6 * v;
+  if (T.child[c] >= 0) {
+    const Acc nan = (Acc)__builtin_nan("");
+#pragma unroll
+    for (int comp = 0; comp < 6; ++comp) out[comp] = nan;
+    return;
+  }
+  int lev0, I[3];
+  cell_coords(T, c, lev0, I);
+  const int V[3] = {I[0] + (v & 1), I[1] + ((v >> 1) & 1), I[2] + ((v >> 2) & 1)};
+  int64_t leaf[8];
+  int lv[8];
+  int lc = 99, lf = -1;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    lv[o] = octant_leaf(T, l, V, o, leaf[o]);
+    lc = min(lc, lv[o]);
+    lf = max(lf, lv[o]);
+  }
+  Acc res[6] = {0, 0, 0, 0, 0, 0};
+  const int s = l - lc;
+  const int mask = (1 << s) - 1;
+  const bool fr[3] = {(V[0] & mask) != 0, (V[1] & mask) != 0, (V[2] & mask) != 0};
+  if (fr[0] || fr[1] || fr[2]) {
+    // hanging: mean of the coarse leaf's corners spanning the edge / face
+    int oc = 0;
+#pragma unroll
+    for (int o = 7; o >= 0; --o)
+      if (lv[o] == lc) oc = o;
+    int lcc, IC[3];
+    cell_coords(T, leaf[oc], lcc, IC);
+    int cnt = 0;
+    for (int sel = 0; sel < 8; ++sel) {
+      int corner = 0;
+      bool skip = false;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int bit = (sel >> a) & 1;
+        int cb;
+        if (fr[a]) {
+          cb = bit;
+        } else {
+          if (bit) skip = true;
+          cb = (V[a] >> s) - IC[a];
+        }
+        corner |= cb << a;
+      }
+      if (skip) continue;
+      const Acc* src = cv + 48 * leaf[oc] + 6 * corner;
+#pragma unroll
+      for (int comp = 0; comp < 6; ++comp) res[comp] += src[comp];
+      ++cnt;
+    }
+    const Acc inv = (Acc)1 / (Acc)cnt;
+#pragma unroll
+    for (int comp = 0; comp < 6; ++comp) res[comp] *= inv;
+  } else if (lc == lf) {
+    // regular: mean of the eight centre values
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+#pragma unroll
+      for (int comp = 0; comp < 6; ++comp) res[comp] += tc[6 * leaf[o] + comp];
+#pragma unroll
+    for (int comp = 0; comp < 6; ++comp) res[comp] *= (Acc)0.125;
+  } else {
+    // boundary vertex: Eqs. (alphac3d), (alphaf3d)
+    int n_coarse = 0, nfv[8], sum_fv = 0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      nfv[o] = 0;
+      if (lv[o] == lc) {
+        ++n_coarse;
+        continue;
+      }
+      int lj, Ij[3];
+      cell_coords(T, leaf[o], lj, Ij);
+      int cntv = 0;
+      for (int w = 0; w < 8; ++w) {
+        const int W[3] = {Ij[0] + (w & 1), Ij[1] + ((w >> 1) & 1), Ij[2] + ((w >> 2) & 1)};
+        bool touch = false;
+        for (int o2 = 0; o2 < 8 && !touch; ++o2) {
+          const int J[3] = {W[0] - 1 + (o2 & 1), W[1] - 1 + ((o2 >> 1) & 1),
+                            W[2] - 1 + ((o2 >> 2) & 1)};
+          int64_t cc;
+          touch = descend(T, lj, J, cc) == lc;
+        }
+        cntv += touch;
+      }
+      nfv[o] = cntv;
+      sum_fv += cntv;
+    }
+    const Acc ac = (Acc)1 / ((Acc)n_coarse + (Acc)0.125 * (Acc)sum_fv);
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const Acc w = lv[o] == lc ? ac : (Acc)0.125 * (Acc)nfv[o] * ac;
+#pragma unroll
+      for (int comp = 0; comp < 6; ++comp) res[comp] += w * tc[6 * leaf[o] + comp];
+    }
+  }
+#pragma unroll
+  for (int comp = 0; comp < 6; ++comp) out[comp] = res[comp];
+}
+
+// ------------------------------------------------------------------- march --
+__device__ __forceinline__ int slab_child(double o, double d, double r, int m, int l, double chi) {
+  const double hl1 = ldexp(1.0, -(l + 1));
+  const int mid = 2 * m + 1;
+  if (d == 0.0) return (o / hl1) >= (double)mid;
+  const double tm = tplane((double)mid * hl1, o, r);
+  return d > 0.0 ? (chi > tm) : (chi <= tm);
+}
+
+template <typename R>
+__device__ __forceinline__ void load_block(const R* __restrict__ cv, int64_t cell, const R* P,
+                                           R* q);
+template <>
+__device__ __forceinline__ void load_block<float>(const float* __restrict__ cv, int64_t cell,
+                                                  const float* P, float* q) {
+  const float4* p = reinterpret_cast<const float4*>(cv + 48 * cell);
+  float t[48];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const float4 x = p[i];
+    t[4 * i] = x.x; t[4 * i + 1] = x.y; t[4 * i + 2] = x.z; t[4 * i + 3] = x.w;
+  }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    float acc = P[0] * t[6 * v];
+#pragma unroll
+    for (int c = 1; c < 6; ++c) acc = fmaf(P[c], t[6 * v + c], acc);
+    q[v] = acc;
+  }
+}
+template <>
+__device__ __forceinline__ void load_block<double>(const double* __restrict__ cv, int64_t cell,
+                                                   const double* P, double* q) {
+  const double2* p = reinterpret_cast<const double2*>(cv + 48 * cell);
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const double2 a = p[3 * v], b = p[3 * v + 1], c = p[3 * v + 2];
+    double acc = P[0] * a.x;
+    acc = fma(P[1], a.y, acc);
+    acc = fma(P[2], b.x, acc);
+    acc = fma(P[3], b.y, acc);
+    acc = fma(P[4], c.x, acc);
+    acc = fma(P[5], c.y, acc);
+    q[v] = acc;
+  }
+}
+
+template <typename R, bool kDebug>
+__device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceArgs& a,
+                          const DevBundle& B, int64_t ray) {
+  const int64_t out = B.ray_offset + ray;
+  const double d[3] = {B.dir[3 * ray + 0], B.dir[3 * ray + 1], B.dir[3 * ray + 2]};
+  const double nrm2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  if (!(fabs(nrm2 - 1.0) <= 1e-9)) {
+    if (a.status) a.status[out] = RR_RAY_BAD_DIRECTION;
+    return;
+  }
+  double Pd[6];
+  projection(a.quantity, d[0], d[1], d[2], Pd);
+  R P[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) P[c] = (R)Pd[c];
+  double r[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r[k] = (d[k] != 0.0) ? 1.0 / d[k] : 0.0;
+
+  const double lo = B.chi_lo;
+  double chiA = B.chi_hi;
+  int m[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m[k] = start_slab(a.o[k], d[k], r[k], chiA, 1.0);
+  int l = 0;
+  int64_t cell = base_of(T, 0, m);
+  {
+    int k;
+    while ((k = T.child[cell]) >= 0) {
+      int ch = 0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const int bit = slab_child(a.o[ax], d[ax], r[ax], m[ax], l, chiA);
+        m[ax] = 2 * m[ax] + bit;
+        ch |= bit << ax;
+      }
+      cell = T.nb + 8 * (int64_t)k + ch;
+      ++l;
+    }
+  }
+
+  const R inv_chis = (R)(1.0 / B.chi_s);
+  const R scale = (R)a.kappa_scale;
+  R sum;
+  float comp = 0.0f;
+  if constexpr (sizeof(R) == 4) {
+    sum = reinterpret_cast<float*>(a.kappa)[out];
+    if (a.kappa_comp) comp = a.kappa_comp[out];
+  } else {
+    sum = reinterpret_cast<double*>(a.kappa)[out];
+  }
+  uint64_t hv = kFnvOffset;
+  int64_t count = 0;
+  int32_t st = RR_RAY_OK;
+  const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
+
+  for (;;) {
+    if (count >= maxc) {
+      st = RR_RAY_MAX_STEPS;
+      break;
+    }
+    const double hl = ldexp(1.0, -l), inv_hl = ldexp(1.0, l);
+    double te[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      te[k] = d[k] != 0.0 ? tplane((double)(d[k] > 0.0 ? m[k] : m[k] + 1) * hl, a.o[k], r[k])
+                          : -__builtin_inf();
+    double chiB = lo;
+    chiB = te[0] > chiB ? te[0] : chiB;
+    chiB = te[1] > chiB ? te[1] : chiB;
+    chiB = te[2] > chiB ? te[2] : chiB;
+    bool stepped[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
+
+    R q[8];
+    load_block<R>(cv, cell, P, q);
+    R uA[3], uB[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double base = a.o[k] - (double)m[k] * hl;
+      uA[k] = (R)(fma(chiA, d[k], base) * inv_hl);
+      const R face = d[k] > 0.0 ? (R)0 : (R)1;
+      uB[k] = stepped[k] ? face : (R)(fma(chiB, d[k], base) * inv_hl);
+    }
+    const R L = (R)(chiA - chiB);
+    const R ic = cell_integral<R>(q, uA, uB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+    if constexpr (sizeof(R) == 4) {
+      kahan_add(sum, comp, ic);
+    } else {
+      sum += ic;
+    }
+    if constexpr (kDebug) {
+      if (a.hash) hv = fnv_piece(hv, cell, chiA, chiB);
+      if (a.log && count < a.log_stride) {
+        LogRecord* L0 = reinterpret_cast<LogRecord*>(a.log) + out * a.log_stride + count;
+        L0->cell = cell;
+        L0->chi_a = chiA;
+        L0->chi_b = chiB;
+      }
+    }
+    ++count;
+    if (chiB == lo) break;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (stepped[k]) m[k] += d[k] > 0.0 ? -1 : 1;
+    chiA = chiB;
+    // the leaf just past the crossed face(s)
+    int64_t nc;
+    const int lev = descend(T, l, m, nc);
+    if (lev < l) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) m[k] >>= (l - lev);
+      l = lev;
+    } else {
+      int k;
+      while ((k = T.child[nc]) >= 0) {
+        int ch = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const int bit = stepped[ax] ? (d[ax] > 0.0 ? 1 : 0)
+                                      : slab_child(a.o[ax], d[ax], r[ax], m[ax], l, chiA);
+          m[ax] = 2 * m[ax] + bit;
+          ch |= bit << ax;
+        }
+        nc = T.nb + 8 * (int64_t)k + ch;
+        ++l;
+      }
+    }
+    cell = nc;
+  }
+  if (!(sum == sum) || sum - sum != (R)0) st = RR_RAY_NONFINITE;
+  if constexpr (sizeof(R) == 4) {
+    reinterpret_cast<float*>(a.kappa)[out] = sum;
+    if (a.kappa_comp) a.kappa_comp[out] = comp;
+  } else {
+    reinterpret_cast<double*>(a.kappa)[out] = sum;
+  }
+  if (a.status) a.status[out] = st;
+  if constexpr (kDebug) {
+    if (a.hash) a.hash[out] = hv;
+    if (a.count) a.count[out] = count;
+  }
+}
+
+template <typename R, bool kDebug>
+__device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const TraceArgs& a,
+                                         int64_t tile, int lane) {
+  const int b = find_bundle(a.bundles, a.n_bundles, tile);
+  const DevBundle& B = a.bundles[b];
+  const int64_t local = tile - B.tile_begin;
+  const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
+  const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
+  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug>(T, cv, a, B, (int64_t)iy * B.nx + ix);
+}
+
+template <typename R, bool kDebug>
+__global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __restrict__ cv,
+                                                           TraceArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nblk = gridDim.x, blk = blockIdx.x;
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t tile = ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + wave;
+  if (tile >= a.n_tiles) return;
+  oct_tile<R, kDebug>(T, cv, a, tile, lane);
+}
+
+template <typename R, bool kDebug>
+__global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* __restrict__ cv,
+                                                               TraceArgs a) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    unsigned long long t = 0;
+    if (lane == 0) t = atomicAdd(a.queue, 1ull);
+    t = __shfl(t, 0, 64);
+    if ((int64_t)t >= a.n_tiles) break;
+    oct_tile<R, kDebug>(T, cv, a, (int64_t)t, lane);
+  }
+}
+
+template <typename R, bool kDebug>
+hipError_t launch_march(const Tree& T, const void* cv, const TraceArgs& a, int persistent,
+                        int grid_waves, hipStream_t s) {
+  if (persistent) {
+    const int blocks = (grid_waves + 3) / 4;
+    hipLaunchKernelGGL((march_octree_persistent<R, kDebug>), dim3(blocks), dim3(256), 0, s, T,
+                       (const R*)cv, a);
+  } else {
+    int64_t blocks = (a.n_tiles + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    blocks = (blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL((march_octree_kernel<R, kDebug>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       T, (const R*)cv, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename In, typename Acc>
+hipError_t build_all(const OctreeTensor& t, const void* values, hipStream_t s) {
+  Tree T{t.child_oct_dev, reinterpret_cast<const int4*>(t.oct_info), t.n,
+         (int64_t)t.n * t.n * t.n};
+  for (int l = 0; l <= t.max_level; ++l) {
+    const int64_t b = t.level_begin[l], e = t.level_begin[l + 1];
+    if (e <= b) continue;
+    const int64_t blocks = (e - b + 255) / 256;
+    hipLaunchKernelGGL((centre_kernel<In, Acc>), dim3((unsigned)blocks), dim3(256), 0, s, T,
+                       (const In*)values, (Acc*)t.centre, l, b, e);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  for (int l = 0; l <= t.max_level; ++l) {
+    const int64_t b = t.level_begin[l], e = t.level_begin[l + 1];
+    if (e <= b) continue;
+    const int64_t blocks = (8 * (e - b) + 255) / 256;
+    hipLaunchKernelGGL((corner_kernel<Acc>), dim3((unsigned)blocks), dim3(256), 0, s, T,
+                       (const Acc*)t.centre, (Acc*)t.corners, l, b, e);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t OctreeTensor::build(const void* values, int dtype, hipStream_t s) {
+  if (precision == RR_PREC_FP32_KAHAN)
+    return dtype == RR_F32 ? build_all<float, float>(*this, values, s)
+                           : build_all<double, float>(*this, values, s);
+  return dtype == RR_F32 ? build_all<float, double>(*this, values, s)
+                         : build_all<double, double>(*this, values, s);
+}
+
+hipError_t OctreeTensor::march(const TraceArgs& a, int persistent, int grid_waves,
+                               hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
+  Tree T{child_oct_dev, reinterpret_cast<const int4*>(oct_info), n, (int64_t)n * n * n};
+  const bool dbg = a.hash || a.log || a.count;
+  if (precision == RR_PREC_FP32_KAHAN)
+    return dbg ? launch_march<float, true>(T, corners, a, persistent, grid_waves, s)
+               : launch_march<float, false>(T, corners, a, persistent, grid_waves, s);
+  return dbg ? launch_march<double, true>(T, corners, a, persistent, grid_waves, s)
+             : launch_march<double, false>(T, corners, a, persistent, grid_waves, s);
+}
+
+}  // namespace rr

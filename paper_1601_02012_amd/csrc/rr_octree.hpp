@@ -18,8 +18,8 @@ struct OctreeTensor {
   int64_t n_cells = 0;
   int64_t n_octs = 0;
   const int32_t* child_oct_dev = nullptr;   // caller-owned
-  int32_t* oct_info = nullptr;              // per oct: level-l coords of child 0 (x,y,z), level
-  float* centre = nullptr;                  // per cell: 6 components (precision-typed storage)
+  int32_t* oct_info = nullptr;              // per oct: level coords of child 0 (x,y,z), level
+  void* centre = nullptr;                   // per cell: 6 components (precision-typed)
   void* corners = nullptr;                  // per cell: 8 x 6 components
   int32_t corner_record_bytes = 0;
   int64_t level_begin[kMaxLevel + 2] = {0};  // first cell index of each level (levels contiguous)

@@ -421,3 +421,208 @@ def random_octree(n: int, max_level: int, p: float, rng: np.random.Generator,
 def full_octree(n: int, level: int) -> OctreeInput:
     """Every cell refined down to ``level`` (equivalent to a uniform n*2^level grid)."""
     return build_octree(n, level, lambda l, c: np.ones(c.shape[0], bool))
+
+
+# ------------------------------------------------------------ AMR light cone --
+RHO_CRIT = 2.77536627e11        # critical density, (Msun/h) / (Mpc/h)^3
+G_NEWTON = 4.30091727e-9        # Mpc (km/s)^2 / Msun
+C_KMS = 299792.458
+
+
+def _nfw_f(c):
+    return np.log1p(c) - c / (1.0 + c)
+
+
+def _nfw_sample_x(u, c, iters=60):
+    """Inverse of the NFW enclosed-mass profile m(x) = ln(1+x) - x/(1+x) on
+    [0, c] (bisection, vectorised); u in [0, m(c)]."""
+    lo = np.zeros_like(u)
+    hi = np.full_like(u, c)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        below = _nfw_f(mid) < u
+        lo = np.where(below, mid, lo)
+        hi = np.where(below, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+@dataclass
+class HaloCatalogue:
+    centres: np.ndarray     # (h, 3) Mpc/h
+    m200: np.ndarray        # Msun/h
+    r200: np.ndarray        # Mpc/h
+    conc: float
+
+
+def amr_particles(n: int = 256, box: float = 256.0, n_part: int = 1 << 24,
+                  halo_frac: float = 0.3, conc: float = 5.0, seed_cfg: int = 3):
+    """Particles of the AMR configuration: NFW haloes (masses log-uniform in
+    [1e12, 1e15] Msun/h, concentration 5, radii truncated at R200) holding
+    ``halo_frac`` of the particles, the rest multinomial-sampled from a
+    lognormal density on the base grid.  Returns (positions, haloes, delta)."""
+    rng_f, rng_h, rng_p, _ = seeds(seed_cfg)
+    m_p = OMEGA_M * RHO_CRIT * (box / n) ** 3 * (n ** 3 / n_part)
+    budget = halo_frac * n_part * m_p
+    masses = []
+    tot = 0.0
+    while tot < budget:
+        m = 10.0 ** rng_h.uniform(12.0, 15.0)
+        if tot + m > budget:
+            break
+        masses.append(m)
+        tot += m
+    masses = np.array(masses)
+    r200 = (3.0 * masses / (4.0 * np.pi * 200.0 * RHO_CRIT)) ** (1.0 / 3.0)
+    centres = rng_h.uniform(0.0, box, size=(len(masses), 3))
+    npart_h = np.maximum(np.round(masses / m_p).astype(np.int64), 1)
+    pos = []
+    fc = _nfw_f(conc)
+    for c0, r2, k in zip(centres, r200, npart_h):
+        x = _nfw_sample_x(rng_p.uniform(0.0, fc, size=k), conc)
+        r = x * (r2 / conc)
+        v = rng_p.normal(size=(k, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        pos.append(c0[None, :] + r[:, None] * v)
+    n_halo = int(npart_h.sum())
+    delta = lognormal_delta(n, box, rng_f, slope=-2.0, sigma_g=1.0)
+    w = (1.0 + delta).ravel()
+    counts = rng_p.multinomial(n_part - n_halo, w / w.sum())
+    cells = np.repeat(np.arange(n ** 3, dtype=np.int64), counts)
+    h = box / n
+    base = np.stack([cells % n, (cells // n) % n, cells // (n * n)], -1).astype(np.float64)
+    pos.append((base + rng_p.uniform(0.0, 1.0, size=base.shape)) * h)
+    pos = np.mod(np.concatenate(pos), box)
+    return pos, HaloCatalogue(centres, masses, r200, conc), delta
+
+
+def amr_octree_from_particles(pos, n: int, box: float, max_level: int = 4,
+                              threshold: int = 8) -> OctreeInput:
+    """Refine every cell holding more than ``threshold`` particles, down to
+    ``max_level``; then 2:1-balance over faces, edges and corners."""
+    h = box / n
+
+    def refine(l, coords):
+        nl = n << l
+        ip = np.floor(pos / (h / (1 << l))).astype(np.int64) % nl
+        keys = (ip[:, 2] * nl + ip[:, 1]) * nl + ip[:, 0]
+        uk, cnt = np.unique(keys, return_counts=True)
+        ck = _key(coords, nl)
+        idx = np.searchsorted(uk, ck)
+        idx = np.minimum(idx, len(uk) - 1)
+        found = uk[idx] == ck
+        return found & (cnt[idx] > threshold)
+
+    return build_octree(n, max_level, refine)
+
+
+def _trilinear_periodic(field, pts_cells):
+    """Trilinear interpolation of a periodic cell-centred field [z][y][x] at
+    points given in cell units (cell centres at i + 0.5)."""
+    n = field.shape[0]
+    p = pts_cells - 0.5
+    i0 = np.floor(p).astype(np.int64)
+    f = p - i0
+    out = np.zeros(p.shape[0])
+    for dz in (0, 1):
+        wz = f[:, 2] if dz else 1.0 - f[:, 2]
+        for dy in (0, 1):
+            wy = f[:, 1] if dy else 1.0 - f[:, 1]
+            for dx in (0, 1):
+                wx = f[:, 0] if dx else 1.0 - f[:, 0]
+                out += wx * wy * wz * field[(i0[:, 2] + dz) % n, (i0[:, 1] + dy) % n,
+                                            (i0[:, 0] + dx) % n]
+    return out
+
+
+def amr_potential(t: OctreeInput, box: float, haloes: HaloCatalogue, delta) -> np.ndarray:
+    """Phi/c^2 at every cell centre (leaf and refined cells): the Poisson
+    potential of the lognormal background interpolated to the centre, plus a
+    truncated NFW potential per halo inside 2 R200 (shifted to zero there)."""
+    n = t.n
+    h = box / n
+    phi_bg = poisson_phi(delta, box)
+    cen = t.centres(box)
+    phi = _trilinear_periodic(phi_bg, cen / h)
+    # cells grouped by base cell for the halo neighbourhood queries
+    base = (t.cell_coord >> t.cell_level[:, None].astype(np.int64))
+    bkey = (base[:, 2] * n + base[:, 1]) * n + base[:, 0]
+    order = np.argsort(bkey, kind="stable")
+    sk = bkey[order]
+    starts = np.searchsorted(sk, np.arange(n ** 3 + 1))
+    c = haloes.conc
+    fc = _nfw_f(c)
+    for c0, m, r2 in zip(haloes.centres, haloes.m200, haloes.r200):
+        rs = r2 / c
+        rt = 2.0 * r2
+        amp = G_NEWTON * m / fc / C_KMS ** 2
+        phi_t = -amp * np.log1p(rt / rs) / rt
+        lo = np.floor((c0 - rt) / h).astype(np.int64)
+        hi = np.floor((c0 + rt) / h).astype(np.int64)
+        rng_ax = [np.arange(lo[a], hi[a] + 1) % n for a in range(3)]
+        bz, by, bx = np.meshgrid(rng_ax[2], rng_ax[1], rng_ax[0], indexing="ij")
+        bk = ((bz * n + by) * n + bx).ravel()
+        segs = [order[starts[b]:starts[b + 1]] for b in bk]
+        cells = np.concatenate(segs) if segs else np.zeros(0, np.int64)
+        dvec = cen[cells] - c0[None, :]
+        dvec -= box * np.round(dvec / box)
+        r = np.sqrt(np.sum(dvec * dvec, axis=1))
+        inside = r < rt
+        rr = np.maximum(r[inside], 1e-6 * rs)
+        phi[cells[inside]] += -amp * np.log1p(rr / rs) / rr - phi_t
+    return phi
+
+
+@dataclass
+class AmrCase:
+    tree: OctreeInput
+    box: float
+    phi: np.ndarray
+    haloes: HaloCatalogue
+    observer: tuple = (0.0, 0.0, 0.0)
+
+
+def config3(n: int = 256, box: float = 256.0, n_part: int = 1 << 24, max_level: int = 4):
+    """AMR octree: 256^3 base grid, refinement where a cell holds > 8 of 2^24
+    particles (NFW haloes on a lognormal background), up to 4 levels."""
+    pos, haloes, delta = amr_particles(n, box, n_part)
+    t = amr_octree_from_particles(pos, n, box, max_level)
+    del pos
+    phi = amr_potential(t, box, haloes, delta)
+    return AmrCase(t, box, phi, haloes)
+
+
+def config3_rays(nray: int = 4096, fov_deg: float = 10.0):
+    fov = math.radians(fov_deg)
+    chi_s = chi_of_z(1.0)
+    d = fov_directions((0.0, 0.0, 1.0), fov, fov, nray, nray)
+    return Bundle(d, nray, nray, chi_s, chi_s, 0.0, (0.0, 0.0, 1.0), fov, fov)
+
+
+@dataclass
+class BundleSpec:
+    side: int
+    z_s: float
+    chi_s: float
+    fov: float
+    center: tuple
+
+
+def config4_specs(n_bundles: int = 64):
+    """64 bundles: side 8*round(32*2^U) with U ~ U[0, 3] (256..2048 rays per
+    side), z_s ~ U[0.5, 2], square field of view ~ U[1, 10] deg, centre
+    directions uniform on the sphere."""
+    _, _, _, rb = seeds(4)
+    out = []
+    for _ in range(n_bundles):
+        side = int(8 * round(32 * 2.0 ** rb.uniform(0.0, 3.0)))
+        zs = float(rb.uniform(0.5, 2.0))
+        fov = math.radians(float(rb.uniform(1.0, 10.0)))
+        v = rb.normal(size=3)
+        v /= np.linalg.norm(v)
+        out.append(BundleSpec(side, zs, chi_of_z(zs), fov, tuple(v)))
+    return out
+
+
+def bundle_from_spec(s: BundleSpec) -> Bundle:
+    d = fov_directions(s.center, s.fov, s.fov, s.side, s.side)
+    return Bundle(d, s.side, s.side, s.chi_s, s.chi_s, 0.0, s.center, s.fov, s.fov)
