@@ -198,6 +198,19 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp,
                         const rr_bundle* bundles /* host */, int32_t n_bundles, void* kappa,
                         float* kappa_comp, int32_t* ray_status, rr_stream s);
 
+/* Tune the launch shape for this bundle set: times one-wavefront-per-tile
+ * launches (64- and 256-thread workgroups) and persistent workgroups fed by
+ * the device queue (8, 16 or 32 wavefronts per compute unit) on scratch
+ * outputs, and remembers the fastest for the bundle set; later rr_trace_rays
+ * calls with tp->persistent = -1 and the same bundles use it.  Synchronous;
+ * allocates and frees scratch buffers; never called inside a capture. */
+rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,
+                           const rr_bundle* bundles, int32_t n_bundles, rr_stream s);
+/* The shape chosen by rr_plan_autotune for a bundle set (and its time in ms). */
+rr_status rr_plan_tuned_shape(rr_plan p, const rr_bundle* bundles, int32_t n_bundles,
+                              int32_t* persistent, int32_t* block, int32_t* waves_per_cu,
+                              float* ms);
+
 /* Gradient of L = sum_r w_r kappa_r with respect to the potential values of
  * a uniform periodic FP32 field: ADDS dL/dPhi to dl_dphi (device, n_base^3
  * FP32, same layout as f->values).  kappa is linear in Phi (straight rays,

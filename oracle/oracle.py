@@ -71,6 +71,7 @@ def lib():
         L.rro_octree_check.restype = i32
         L.rro_centre_tensor_octree.argtypes = [vp, vp, vp]
         L.rro_corner_tensor_octree.argtypes = [vp, vp, vp]
+        L.rro_corner_tensor_octree_cells.argtypes = [vp, vp, i64, vp, vp]
         L.rro_vertex_weights.argtypes = [i32, i32, i32, vp, vp, vp]
         L.rro_trace_octree.argtypes = [vp, dbl, vp, i64, vp, vp, vp, vp, dbl, vp, vp, i64, i32,
                                        vp, vp, vp, vp, vp, i64]
@@ -217,6 +218,14 @@ def centre_tensor_octree(t: Octree, phi):
 def corner_tensor_octree(t: Octree, tc):
     cv = np.empty((t.n_cells, 8, 6))
     lib().rro_corner_tensor_octree(t.ref(), _p(_f64(tc)), _p(cv))
+    return cv
+
+
+def corner_tensor_octree_cells(t: Octree, tc, cells):
+    """Corner tensors (n, 8, 6) of the listed leaf cells only."""
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    cv = np.empty((cells.shape[0], 8, 6))
+    lib().rro_corner_tensor_octree_cells(t.ref(), _p(_f64(tc)), cells.shape[0], _p(cells), _p(cv))
     return cv
 
 

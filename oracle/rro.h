@@ -103,6 +103,9 @@ void rro_centre_tensor_octree(const rro_octree* t, const double* phi, double* tc
 /* Corner tensors of every leaf: cv[c*48 + v*6 + comp], v = ix + 2 iy + 4 iz.
  * Regular / boundary (Eqs. alphac3d, alphaf3d) / hanging vertices. */
 void rro_corner_tensor_octree(const rro_octree* t, const double* tc, double* cv /* n_cells x 48 */);
+/* The same for a list of leaf cells only (cv: n_sel x 48). */
+void rro_corner_tensor_octree_cells(const rro_octree* t, const double* tc, int64_t n_sel,
+                                    const int64_t* cells, double* cv);
 /* 3D mass-redistribution weights: alpha_coarse and alpha_fine for one vertex,
  * for dimension dim (2: Eqs. alphaconst/alphaconst2, 3: Eqs. alphac3d/alphaf3d). */
 void rro_vertex_weights(int32_t dim, int32_t n_coarse, int32_t n_fine, const int32_t* n_fv,

@@ -307,6 +307,16 @@ void rro_corner_tensor_octree(const rro_octree* t, const double* tc, double* cv)
   }
 }
 
+void rro_corner_tensor_octree_cells(const rro_octree* t, const double* tc, int64_t n_sel,
+                                    const int64_t* cells, double* cv /* n_sel x 48 */) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t s = 0; s < n_sel; ++s) {
+    double tmp[8][6];
+    leaf_corners(t, tc, cells[s], tmp);
+    memcpy(cv + 48 * s, tmp, sizeof(tmp));
+  }
+}
+
 /* ------------------------------------------------------------------- tracing */
 /* child bit on axis a when moving from level l slab m to level l+1 at chi */
 static int slab_child(const rro_ray* ray, int a, int64_t m, int32_t l, double chi) {

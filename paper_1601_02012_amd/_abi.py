@@ -60,6 +60,9 @@ SIGNATURES = [
                              _vp, _vp]),
     ("rr_trace_rays_adjoint", _i32, [_vp, _vp, C.POINTER(FieldDesc), C.POINTER(TraceParams),
                                      C.POINTER(Bundle), _i32, _vp, _vp, _vp]),
+    ("rr_plan_autotune", _i32, [_vp, _vp, C.POINTER(TraceParams), C.POINTER(Bundle), _i32, _vp]),
+    ("rr_plan_tuned_shape", _i32, [_vp, C.POINTER(Bundle), _i32, C.POINTER(_i32), C.POINTER(_i32),
+                                   C.POINTER(_i32), C.POINTER(C.c_float)]),
     ("rr_graph_begin", _i32, [_vp, _vp]),
     ("rr_graph_end", _i32, [_vp, _vp]),
     ("rr_graph_launch", _i32, [_vp, _vp]),

@@ -152,6 +152,20 @@ class Plan:
         A.check("rr_plan_create", _lib.rr_plan_create(C.byref(h)))
         self.handle = h
 
+    def autotune(self, tensor: "TidalTensor", bundles, observer, *, kappa_scale=1.0,
+                 quantity="kappa", stream=None):
+        """rr_plan_autotune: pick the fastest launch shape for these bundles."""
+        tp = _params(observer, tensor.precision, quantity, kappa_scale, -1)
+        arr = _bundle_array(bundles)
+        A.check("rr_plan_autotune", _lib.rr_plan_autotune(self.handle, tensor.handle, C.byref(tp),
+                                                          arr, len(bundles), _stream(stream)))
+        pers, blk, wpc, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+        A.check("rr_plan_tuned_shape",
+                _lib.rr_plan_tuned_shape(self.handle, arr, len(bundles), C.byref(pers),
+                                         C.byref(blk), C.byref(wpc), C.byref(ms)))
+        return {"persistent": pers.value, "block": blk.value, "waves_per_cu": wpc.value,
+                "ms": ms.value}
+
     def graph_begin(self, stream=None):
         A.check("rr_graph_begin", _lib.rr_graph_begin(self.handle, _stream(stream)))
 

@@ -66,6 +66,15 @@ struct CachedTable {
   int64_t n_tiles = 0;
 };
 
+// Launch shape chosen by rr_plan_autotune for one bundle set.
+struct TunedShape {
+  std::vector<rr_bundle> key;
+  int32_t persistent = 0;
+  int32_t block = 256;
+  int32_t waves_per_cu = 16;
+  float ms = 0.0f;
+};
+
 }  // namespace
 
 struct rr_plan_s {
@@ -74,9 +83,10 @@ struct rr_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int cu_count = 0;
-  int waves_per_cu = 0;      // persistent occupancy target
-  int prefer_persistent = 0; // tuner result
+  int waves_per_cu = 0;      // persistent occupancy target (default)
+  int prefer_persistent = 0; // default when the caller passes persistent = -1
   int device = 0;
+  std::vector<TunedShape> tuned;
 };
 
 namespace {
@@ -337,6 +347,26 @@ rr_status get_table(rr_plan p, rr_tensor t, const rr_bundle* b, int32_t nb, int 
 
 }  // namespace
 
+}  // extern "C"
+
+namespace {
+
+rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
+                       int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
+                       hipStream_t hs, int persistent, int block, int waves_per_cu);
+
+const TunedShape* find_tuned(rr_plan p, const rr_bundle* b, int32_t nb) {
+  for (const auto& x : p->tuned)
+    if ((int32_t)x.key.size() == nb &&
+        (nb == 0 || std::memcmp(x.key.data(), b, sizeof(rr_bundle) * nb) == 0))
+      return &x;
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
 rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
                         int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
                         rr_stream s) {
@@ -349,7 +379,111 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp, const
   if (tp->quantity != RR_Q_KAPPA && t->kind == RR_GRID_OCTREE)
     return fail(RR_ERR_UNSUPPORTED, "shear on octrees is not implemented");
   const hipStream_t hs = (hipStream_t)s;
-  const int persistent = tp->persistent < 0 ? p->prefer_persistent : (tp->persistent ? 1 : 0);
+  int persistent = tp->persistent < 0 ? p->prefer_persistent : (tp->persistent ? 1 : 0);
+  int block = 256, waves_per_cu = p->waves_per_cu;
+  if (tp->persistent < 0) {
+    if (const TunedShape* ts = find_tuned(p, bundles, n_bundles)) {
+      persistent = ts->persistent;
+      block = ts->block;
+      waves_per_cu = ts->waves_per_cu;
+    }
+  }
+  return launch_trace(p, t, tp, bundles, n_bundles, kappa, kappa_comp, ray_status, hs, persistent,
+                      block, waves_per_cu);
+}
+
+rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,
+                           const rr_bundle* bundles, int32_t n_bundles, rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  rr_status st = validate_trace(t, tp, bundles, n_bundles);
+  if (st != RR_OK) return st;
+  const hipStream_t hs = (hipStream_t)s;
+  if (capturing(hs)) return fail(RR_ERR_CAPACITY, "autotuning cannot run inside a capture");
+  int64_t nr = 0;
+  for (int32_t i = 0; i < n_bundles; ++i)
+    nr = std::max<int64_t>(nr, bundles[i].ray_offset + bundles[i].n_rays);
+  if (nr == 0) return RR_OK;
+  const size_t kb = (size_t)nr * (t->precision == RR_PREC_FP32_KAHAN ? 4 : 8);
+  void *kap = nullptr, *comp = nullptr, *stat = nullptr;
+  hipError_t e = hipMalloc(&kap, kb);
+  if (e == hipSuccess) e = hipMalloc(&comp, (size_t)nr * 4);
+  if (e == hipSuccess) e = hipMalloc(&stat, (size_t)nr * 4);
+  if (e != hipSuccess) {
+    if (kap) (void)hipFree(kap);
+    if (comp) (void)hipFree(comp);
+    return fail(RR_ERR_OOM, "autotune scratch: %s", hipGetErrorString(e));
+  }
+  rr_trace_params q = *tp;
+  q.crossing_hash = nullptr;
+  q.crossing_count = nullptr;
+  q.crossing_log = nullptr;
+  q.log_stride = 0;
+  struct Cand { int persistent, block, waves; };
+  const Cand cands[] = {{0, 256, 0}, {0, 64, 0}, {1, 256, 8}, {1, 256, 16}, {1, 256, 32}};
+  hipEvent_t e0, e1;
+  RR_HIP(hipEventCreate(&e0), "event");
+  RR_HIP(hipEventCreate(&e1), "event");
+  TunedShape best;
+  best.key.assign(bundles, bundles + n_bundles);
+  best.ms = 1e30f;
+  for (const Cand& c : cands) {
+    float ms_best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {   // first run also uploads the bundle table
+      RR_HIP(hipEventRecord(e0, hs), "event record");
+      st = launch_trace(p, t, &q, bundles, n_bundles, kap, (float*)comp, (int32_t*)stat, hs,
+                        c.persistent, c.block, c.waves ? c.waves : p->waves_per_cu);
+      if (st != RR_OK) break;
+      RR_HIP(hipEventRecord(e1, hs), "event record");
+      RR_HIP(hipEventSynchronize(e1), "event sync");
+      float ms = 0.0f;
+      RR_HIP(hipEventElapsedTime(&ms, e0, e1), "event time");
+      if (rep > 0) ms_best = std::min(ms_best, ms);
+    }
+    if (st != RR_OK) break;
+    if (ms_best < best.ms) {
+      best.ms = ms_best;
+      best.persistent = c.persistent;
+      best.block = c.block;
+      best.waves_per_cu = c.waves ? c.waves : p->waves_per_cu;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(kap);
+  (void)hipFree(comp);
+  (void)hipFree(stat);
+  if (st != RR_OK) return st;
+  for (auto& x : p->tuned)
+    if (x.key.size() == best.key.size() &&
+        std::memcmp(x.key.data(), best.key.data(), sizeof(rr_bundle) * x.key.size()) == 0) {
+      x = best;
+      return RR_OK;
+    }
+  p->tuned.push_back(best);
+  return RR_OK;
+}
+
+rr_status rr_plan_tuned_shape(rr_plan p, const rr_bundle* bundles, int32_t n_bundles,
+                              int32_t* persistent, int32_t* block, int32_t* waves_per_cu,
+                              float* ms) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  const TunedShape* ts = find_tuned(p, bundles, n_bundles);
+  if (!ts) return fail(RR_ERR_INVALID_ARG, "no tuned shape for this bundle set");
+  if (persistent) *persistent = ts->persistent;
+  if (block) *block = ts->block;
+  if (waves_per_cu) *waves_per_cu = ts->waves_per_cu;
+  if (ms) *ms = ts->ms;
+  return RR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
+                       int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
+                       hipStream_t hs, int persistent, int block, int waves_per_cu) {
+  rr_status st;
   const CachedTable* tab = nullptr;
   st = get_table(p, t, bundles, n_bundles, persistent, hs, &tab);
   if (st != RR_OK) return st;
@@ -375,16 +509,20 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp, const
   a.log = tp->crossing_log;
   a.log_stride = tp->log_stride;
   a.queue = p->queue;
-  const int grid_waves = p->cu_count * p->waves_per_cu;
+  const int grid_waves = p->cu_count * waves_per_cu;
   if (persistent) RR_HIP(rr::launch_queue_reset(p->queue, hs), "queue reset");
   if (t->kind == RR_GRID_UNIFORM) {
-    RR_HIP(rr::launch_march_uniform(t->precision, t->data, a, persistent, 256, grid_waves, hs),
+    RR_HIP(rr::launch_march_uniform(t->precision, t->data, a, persistent, block, grid_waves, hs),
            "march launch");
   } else {
     RR_HIP(t->oct->march(a, persistent, grid_waves, hs), "octree march launch");
   }
   return RR_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
                                 const rr_trace_params* tp, const rr_bundle* bundles,

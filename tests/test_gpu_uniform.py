@@ -279,3 +279,18 @@ def test_graph_capture_replays_match_eager(api, plan):
         s.synchronize()
         assert torch.equal(kap, eager), rep
         _ = (kap * 2).sum().item()             # unrelated eager work between replays
+
+
+def test_autotune_choice_gives_identical_results(api, plan):
+    """rr_plan_autotune picks a launch shape; tracing with persistent=-1 then
+    uses it and returns the same per-ray values as the direct launch."""
+    n, box = 32, 64.0
+    phi, dirs = small_periodic_case(seed=12, n=n, box=box, nx=48, ny=40)
+    g = gpu_grid(api, phi.astype(np.float32), box)
+    t = api.TidalTensor(g, "fp32").build()
+    b = gpu_bundle(api, dirs, 48, 40, 90.0, 80.0, 0.0)
+    shape = plan.autotune(t, [b], (0, 0, 0))
+    assert shape["persistent"] in (0, 1) and shape["block"] in (64, 256) and shape["ms"] > 0
+    a = api.trace(plan, t, [b], (0, 0, 0), persistent=0)
+    c = api.trace(plan, t, [b], (0, 0, 0), persistent=-1)
+    assert np.array_equal(a.kappa.cpu().numpy(), c.kappa.cpu().numpy())
