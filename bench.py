@@ -1,23 +1,29 @@
 """Throughput benchmark of the Method-B convergence path on one MI355X.
 
-Workload (the light-cone configuration): a uniform periodic 512^3 grid of
-1 Gpc/h holding an FP32 potential from a seeded lognormal density, 2048^2
-rays over 5 x 5 deg from the box corner to chi_s = chi(z = 1), advanced in
-20 chi segments (one per synthetic N-body step, potential rescaled by the
-linear growth of each step).  One step = the whole light cone: for each of the
-20 segments, build the vertex tensor of that step's potential and march every
-ray through the segment.  The FP32-Kahan path is timed and compared with the
-plain FP64 path on the same inputs; the FP64 CPU oracle is timed on a bounded
-sample of the same workload on the host cores.
+Headline workload (the light cone): a uniform periodic 512^3 grid of 1 Gpc/h
+holding an FP32 potential from a seeded lognormal density, 2048^2 rays over
+5 x 5 deg from the box corner to chi_s = chi(z = 1), advanced in 20 chi
+segments (one per synthetic N-body step, potential rescaled by the linear
+growth of each step).  One step = the whole light cone: for each segment,
+build the vertex tensor of that step's potential over the whole grid and march
+every ray through the segment.  The FP32-Kahan path is timed against the plain
+FP64 path on the same inputs.
 
-Prints one JSON line (rank 0).
+Further legs (reported beside the headline, not in ``value``): the AMR octree
+(256^3 base + 4 levels, 4096^2 rays to z = 1) and the batched set of 64
+uneven bundles through it in one persistent launch replayed from a HIP graph.
+The FP64 CPU oracle is timed on a bounded sample of the light cone.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -27,56 +33,63 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_CROSSING = {"fp32": 96, "fp64": 192}    # 4 new corners x 6 components
-BYTES_PER_VERTEX = {"fp32": 4 + 24, "fp64": 4 + 48}
+BYTES_PER_CROSSING = {"fp32": 96, "fp64": 192}     # 4 new corners x 6 components
+BYTES_PER_VERTEX = {"fp32": 4 + 24, "fp64": 4 + 48}  # potential in, 6 components out
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_traffic.md")
+MARCH_SOURCES = ["paper_1601_02012_amd/csrc/rr_march_uniform.hip",
+                 "paper_1601_02012_amd/csrc/rr_ray.hpp",
+                 "paper_1601_02012_amd/csrc/rr_internal.hpp"]
 
 
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--rays", type=int, default=2048)
-    ap.add_argument("--segments", type=int, default=20)
-    ap.add_argument("--persistent", type=int, default=-1)
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=8192)
-    ap.add_argument("--profile-steps", action="store_true",
-                    help="short run for profilers: skip the CPU baseline and the FP64 leg")
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="after the timed steps, copy this many MiB device-to-device (a plain "
-                         "copy kernel that calibrates the profiler's byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.profile_steps:
-        args.no_fp64 = True
-        args.no_cpu = True
+def march_source_hash():
+    h = hashlib.sha256()
+    for f in MARCH_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
+
+def measured_traffic():
+    """HBM bytes per march launch from the committed rocprofv3 counter summary,
+    if it was taken on the current march source (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_src = re.search(r"march_source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_src or not m_b or m_src.group(1) != march_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def timed(fn, steps, warmup, label):
     import torch
-    from paper_1601_02012_amd import api, inputs as I
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ms = []
+    for s in range(steps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+        log(f"{label} step {s}: {ms[-1]:.2f} ms")
+    return float(np.mean(ms))
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+
+def lightcone_leg(args, api, I, torch, dev):
     n, box = args.n, 1000.0
     nray = args.rays
     fov = math.radians(5.0)
-    log(f"generating inputs: {n}^3 lognormal potential, {nray}^2 rays, {args.segments} segments")
-    t0 = time.time()
+    log(f"light cone: {n}^3 lognormal potential, {nray}^2 rays, {args.segments} segments")
     phi0 = I.config2_phi0(n, box)
     segs = I.lightcone_segments(args.segments)
     chi_s = I.chi_of_z(1.0)
     dirs = I.fov_directions((0.0, 0.0, 1.0), fov, fov, nray, nray)
-    log(f"inputs ready in {time.time() - t0:.1f}s")
-
     phi0_d = torch.as_tensor(phi0, device=dev)
     phis = [(phi0_d * s).to(torch.float32).contiguous() for (_, _, s) in segs]
     del phi0_d
@@ -87,79 +100,239 @@ def main():
     obs = (0.0, 0.0, 0.0)
     nr = nray * nray
     stream = torch.cuda.current_stream()
-
-    def run_step(tensor, kap, comp, st, events=None):
-        for k in range(len(segs)):
-            if events is not None:
-                events[k][0].record(stream)
-            tensor.build(grids[k])
-            if events is not None:
-                events[k][1].record(stream)
-            api.trace(plan, tensor, bundles[k], obs, kappa=kap, kappa_comp=comp, status=st,
-                      persistent=args.persistent)
-            if events is not None:
-                events[k][2].record(stream)
-
     results = {}
     for prec in (["fp32"] + ([] if args.no_fp64 else ["fp64"])):
         t = api.TidalTensor(grids[0], prec)
         fp32 = prec == "fp32"
-        kdt = torch.float32 if fp32 else torch.float64
-        kap = torch.zeros(nr, dtype=kdt, device=dev)
+        kap = torch.zeros(nr, dtype=torch.float32 if fp32 else torch.float64, device=dev)
         comp = torch.zeros(nr, dtype=torch.float32, device=dev) if fp32 else None
         st = torch.zeros(nr, dtype=torch.int32, device=dev)
-        # crossing count of one light cone (untimed debug pass)
         total_cross = 0
+        shapes = []
         for k in range(len(segs)):
             t.build(grids[k])
             o = api.trace(plan, t, bundles[k], obs, debug=True, persistent=0)
             total_cross += int(o.count.sum().item())
-        log(f"{prec}: {total_cross:.4e} crossings per light cone")
-        for w in range(args.warmup):
-            kap.zero_()
-            if comp is not None:
-                comp.zero_()
-            run_step(t, kap, comp, st)
-        torch.cuda.synchronize()
+            del o
+            if not args.no_tune:
+                shapes.append(plan.autotune(t, bundles[k], obs))
+        log(f"{prec}: {total_cross:.4e} crossings per light cone; tuned shapes "
+            f"{sorted(set((s['persistent'], s['block'], s['waves_per_cu']) for s in shapes))}")
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in segs]
-        step_ms, build_ms, march_ms = [], [], []
-        for s in range(args.steps):
+
+        def step():
             kap.zero_()
             if comp is not None:
                 comp.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            run_step(t, kap, comp, st, ev)
-            torch.cuda.synchronize()
-            step_ms.append((time.perf_counter() - t0) * 1e3)
-            build_ms.append(sum(e[0].elapsed_time(e[1]) for e in ev))
-            march_ms.append(sum(e[1].elapsed_time(e[2]) for e in ev))
-            log(f"{prec} step {s}: {step_ms[-1]:.2f} ms (build {build_ms[-1]:.2f}, "
-                f"march {march_ms[-1]:.2f})")
-        stat = st.cpu().numpy()
-        results[prec] = dict(cross=total_cross, step_ms=float(np.mean(step_ms)),
-                             build_ms=float(np.mean(build_ms)), march_ms=float(np.mean(march_ms)),
-                             kappa=kap.double().cpu().numpy(), status_ok=bool(np.all(stat == 0)))
+            for k in range(len(segs)):
+                ev[k][0].record(stream)
+                t.build(grids[k])
+                ev[k][1].record(stream)
+                api.trace(plan, t, bundles[k], obs, kappa=kap, kappa_comp=comp, status=st,
+                          persistent=-1)
+                ev[k][2].record(stream)
+
+        step_ms = timed(step, args.steps, args.warmup, f"light cone {prec}")
+        build_ms = sum(e[0].elapsed_time(e[1]) for e in ev)
+        march_ms = sum(e[1].elapsed_time(e[2]) for e in ev)
+        results[prec] = dict(cross=total_cross, step_ms=step_ms, build_ms=build_ms,
+                             march_ms=march_ms, kappa=kap.double().cpu().numpy(),
+                             status_ok=bool((st == 0).all().item()),
+                             shapes=[(s["persistent"], s["block"], s["waves_per_cu"])
+                                     for s in shapes])
         t.close()
         del kap, comp, st
         torch.cuda.empty_cache()
-
     if args.copy_probe_mib:
         nb = args.copy_probe_mib * (1 << 20)
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe_mib} MiB x 3")
         del src, dst
+    ctx = dict(phis=phis, segs=segs, dirs=dirs, chi_s=chi_s, box=box, obs=obs, n=n)
+    return results, ctx
 
+
+def amr_leg(args, api, I, torch, dev):
+    log("AMR octree: generating 256^3 base + 4 levels from 2^24 particles")
+    t0 = time.time()
+    case = I.config3()
+    tr = case.tree
+    log(f"AMR octree ready in {time.time() - t0:.1f}s: {tr.n_cells} cells, "
+        f"levels {np.bincount(tr.cell_level).tolist()}")
+    grid = api.Grid(torch.as_tensor(case.phi.astype(np.float32), device=dev), case.box,
+                    n_base=tr.n, child_oct=torch.as_tensor(tr.child_oct, device=dev),
+                    max_level=tr.max_level)
+    tens = api.TidalTensor(grid, "fp32")
+    plan = api.Plan()
+    stream = torch.cuda.current_stream()
+    out = {}
+    # AMR light cone: 4096^2 rays over 10 x 10 deg to z = 1
+    b = I.config3_rays(args.amr_rays)
+    nr = b.nx * b.ny
+    gb = [api.RayBundle(torch.as_tensor(b.dirs, device=dev), b.nx, b.ny, b.chi_s, b.chi_hi,
+                        b.chi_lo)]
+    tens.build(grid)
+    cross = int(api.trace(plan, tens, gb, case.observer, debug=True, persistent=0)
+                .count.sum().item())
+    shape = None if args.no_tune else plan.autotune(tens, gb, case.observer)
+    kap = torch.zeros(nr, dtype=torch.float32, device=dev)
+    comp = torch.zeros(nr, dtype=torch.float32, device=dev)
+    st = torch.zeros(nr, dtype=torch.int32, device=dev)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step():
+        kap.zero_()
+        comp.zero_()
+        e[0].record(stream)
+        tens.build(grid)
+        e[1].record(stream)
+        api.trace(plan, tens, gb, case.observer, kappa=kap, kappa_comp=comp, status=st,
+                  persistent=-1)
+        e[2].record(stream)
+
+    ms = timed(step, args.steps, args.warmup, "AMR")
+    out["amr"] = {"workload": f"AMR octree 256^3 base + 4 levels ({tr.n_cells} cells), "
+                              f"{b.nx}x{b.ny} rays over 10x10 deg to z=1, FP32-Kahan",
+                  "crossings": cross, "ms_per_step": ms,
+                  "crossings_per_s": cross / (ms * 1e-3),
+                  "tensor_build_ms": e[0].elapsed_time(e[1]),
+                  "march_ms": e[1].elapsed_time(e[2]),
+                  "march_crossings_per_s": cross / (e[1].elapsed_time(e[2]) * 1e-3),
+                  "all_rays_ok": bool((st == 0).all().item()), "tuned_shape": shape}
+    del kap, comp, st, gb
+    torch.cuda.empty_cache()
+    # batched: 64 uneven bundles, one persistent launch, replayed from a graph
+    specs = I.config4_specs()
+    bundles, offset = [], 0
+    for s in specs:
+        bb = I.bundle_from_spec(s)
+        bundles.append(api.RayBundle(torch.as_tensor(bb.dirs, device=dev), bb.nx, bb.ny,
+                                     bb.chi_s, bb.chi_hi, bb.chi_lo, offset))
+        offset += bb.nx * bb.ny
+    nr = offset
+    cross = int(api.trace(plan, tens, bundles, case.observer, debug=True, persistent=1)
+                .count.sum().item())
+    kap = torch.zeros(nr, dtype=torch.float32, device=dev)
+    comp = torch.zeros(nr, dtype=torch.float32, device=dev)
+    st = torch.zeros(nr, dtype=torch.int32, device=dev)
+    gs = torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        api.trace(plan, tens, bundles, case.observer, kappa=kap, kappa_comp=comp, status=st,
+                  persistent=1)
+        gs.synchronize()
+        plan.graph_begin()
+        api.trace(plan, tens, bundles, case.observer, kappa=kap, kappa_comp=comp, status=st,
+                  persistent=1)
+        plan.graph_end()
+    gs.synchronize()
+
+    def bstep():
+        kap.zero_()
+        comp.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(gs):
+            plan.graph_launch()
+        gs.synchronize()
+
+    ms = timed(bstep, args.steps, args.warmup, "batched")
+    out["batched"] = {"workload": f"{len(specs)} bundles ({nr} rays, sides 256..2048, z_s "
+                                  "0.5..2, FoV 1..10 deg, random centres) through the AMR "
+                                  "octree, one persistent launch in a HIP graph, FP32-Kahan",
+                      "rays": nr, "crossings": cross, "ms_per_step": ms,
+                      "crossings_per_s": cross / (ms * 1e-3),
+                      "all_rays_ok": bool((st == 0).all().item())}
+    tens.close()
+    return out
+
+
+def cpu_baseline(ctx, results, target_s):
+    """FP64 oracle on the host over the whole light cone (every segment with
+    its own vertex tensor) for a deterministic ray sample."""
+    from oracle import oracle as O
+    phis, segs, dirs = ctx["phis"], ctx["segs"], ctx["dirs"]
+    n, box, obs, chi_s = ctx["n"], ctx["box"], ctx["obs"], ctx["chi_s"]
+    cores = os.cpu_count() or 1
     r32 = results["fp32"]
+    per_ray = r32["cross"] / dirs.shape[0]
+    # sample size for about target_s of tracing at ~1e7 crossings/s per core
+    want = int(min(dirs.shape[0], max(4096, target_s * 1.0e7 * cores / per_ray)))
+    rng = np.random.default_rng(12345)
+    sel = np.sort(rng.choice(dirs.shape[0], size=want, replace=False))
+    kap = np.zeros(want)
+    t_tensor = t_trace = 0.0
+    cross = 0
+    for k, (hi, lo, _) in enumerate(segs):
+        phi = phis[k].double().cpu().numpy()
+        t0 = time.perf_counter()
+        tv = O.vertex_tensor(phi)
+        t_tensor += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = O.trace_uniform(n, box, obs, dirs[sel], chi_s, hi, lo, tv=tv, threads=cores)
+        t_trace += time.perf_counter() - t0
+        kap += r.kappa
+        cross += int(r.ncross.sum())
+        del tv
+        log(f"oracle segment {k}: {int(r.ncross.sum())} crossings")
+    log(f"oracle: {want} rays x {len(segs)} segments, {cross} crossings in {t_trace:.1f}s "
+        f"(+{t_tensor:.1f}s tensors)")
+    gk = r32["kappa"][sel]
+    err = np.abs(gk - kap)
+    lim = np.maximum(1e-5 * np.abs(kap), 1e-7)
+    cb = {"value": cross / t_trace, "unit": "crossings/s", "cores": cores, "kind": "oracle",
+          "sample": f"{want} of {dirs.shape[0]} rays through all {len(segs)} chi segments of "
+                    f"the light cone ({cross} crossings); FP64 C oracle, OpenMP over rays; its "
+                    f"{len(segs)} vertex tensors ({n}^3 each) took {t_tensor:.1f}s, not included",
+          "ns_per_crossing_per_core": t_trace * cores / cross * 1e9}
+    par = {"rays": int(want), "kappa_max_err_over_tol": float(np.max(err / lim)),
+           "tolerance": "max(1e-5 |kappa|, 1e-7) per ray, FP32-Kahan GPU vs FP64 oracle"}
+    return cb, par
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--rays", type=int, default=2048)
+    ap.add_argument("--segments", type=int, default=20)
+    ap.add_argument("--amr-rays", type=int, default=4096)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-steps", action="store_true",
+                    help="short light-cone-only run for profilers (no FP64, CPU or AMR legs)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the light cone, copy this many MiB device-to-device (a plain "
+                         "copy kernel that calibrates the profiler's byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.profile_steps:
+        args.no_fp64 = args.no_cpu = args.no_amr = True
+
+    import torch
+    from paper_1601_02012_amd import api, inputs as I
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    results, ctx = lightcone_leg(args, api, I, torch, dev)
+    r32 = results["fp32"]
+    nseg = len(ctx["segs"])
     value = r32["cross"] / (r32["step_ms"] * 1e-3)
-    nseg = len(segs)
     march_launch_ms = r32["march_ms"] / nseg
     cross_per_launch = r32["cross"] / nseg
     achieved = BYTES_PER_CROSSING["fp32"] * cross_per_launch / (march_launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
     out = {
         "metric": "ray-cell crossings/sec and HBM GB/s, FP32-comp vs FP64 at 1e-5 rel kappa err",
         "value": value,
@@ -173,18 +346,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"uniform periodic {n}^3 grid, box 1000 Mpc/h, FP32 lognormal "
-                               f"potential, {nray}x{nray} rays over 5x5 deg, {nseg} chi segments "
-                               "to z=1 (tensor rebuilt per segment), FP32-Kahan march",
-                   "grid": n, "rays": nr, "segments": nseg, "chi_s": chi_s},
+        "config": {"workload": f"light cone: uniform periodic {ctx['n']}^3 grid, box 1000 Mpc/h, "
+                               f"FP32 lognormal potential, {args.rays}x{args.rays} rays over 5x5 "
+                               f"deg, {nseg} chi segments to z=1, tensor rebuilt over the whole "
+                               "grid every segment, FP32-Kahan march",
+                   "grid": ctx["n"], "rays": args.rays ** 2, "segments": nseg,
+                   "chi_s": ctx["chi_s"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic,
                      "kernel": "march_uniform (FP32-Kahan)",
                      "bytes_per_crossing": BYTES_PER_CROSSING["fp32"],
-                     "launch_ms": march_launch_ms, "crossings_per_launch": cross_per_launch},
+                     "launch_ms": march_launch_ms, "crossings_per_launch": cross_per_launch,
+                     "march_source": march_source_hash()},
         "march_crossings_per_s": r32["cross"] / (r32["march_ms"] * 1e-3),
         "tensor_build_ms_per_segment": r32["build_ms"] / nseg,
-        "tensor_build_gbs": BYTES_PER_VERTEX["fp32"] * n ** 3 / (r32["build_ms"] / nseg * 1e-3) / 1e9,
+        "tensor_build_gbs": BYTES_PER_VERTEX["fp32"] * ctx["n"] ** 3
+                            / (r32["build_ms"] / nseg * 1e-3) / 1e9,
+        "tuned_shapes": sorted(set(r32["shapes"])),
         "all_rays_ok": r32["status_ok"],
     }
     if "fp64" in results:
@@ -192,6 +371,7 @@ def main():
         out["fp64_crossings_per_s"] = r64["cross"] / (r64["step_ms"] * 1e-3)
         out["speedup_vs_fp64"] = r64["step_ms"] / r32["step_ms"]
         out["fp64_march_crossings_per_s"] = r64["cross"] / (r64["march_ms"] * 1e-3)
+        out["fp64_tensor_build_ms_per_segment"] = r64["build_ms"] / nseg
         out["crossings_equal_fp32_fp64"] = r64["cross"] == r32["cross"]
         ref = r64["kappa"]
         err = np.abs(r32["kappa"] - ref)
@@ -200,58 +380,13 @@ def main():
                                      "max_abs_err": float(err.max()),
                                      "rms_kappa": float(np.sqrt(np.mean(ref ** 2)))}
     if not args.no_cpu:
-        out["cpu_baseline"], out["oracle_parity_sample"] = cpu_baseline(
-            phis, segs, dirs, chi_s, box, obs, args.cpu_rays, results)
+        out["cpu_baseline"], out["oracle_parity_sample"] = cpu_baseline(ctx, results,
+                                                                        args.cpu_seconds)
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_amr:
+        out.update(amr_leg(args, api, I, torch, dev))
     print(json.dumps(out), flush=True)
-
-
-def cpu_baseline(phis, segs, dirs, chi_s, box, obs, n_sample, results):
-    """FP64 oracle on the host: the vertex tensor of the last segment's
-    potential, then a deterministic sample of rays through that segment."""
-    import torch
-    from oracle import oracle as O
-    k = len(segs) - 1
-    hi, lo, _ = segs[k]
-    phi = phis[k].double().cpu().numpy()
-    n = phi.shape[0]
-    cores = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    tv = O.vertex_tensor(phi)
-    t_tensor = time.perf_counter() - t0
-    rng = np.random.default_rng(12345)
-    perm = rng.permutation(dirs.shape[0])
-    # pilot run, then size the sample to about 15 s of oracle work
-    pilot = np.sort(perm[:min(n_sample, dirs.shape[0])])
-    t0 = time.perf_counter()
-    rp = O.trace_uniform(n, box, obs, dirs[pilot], chi_s, hi, lo, tv=tv, threads=cores)
-    tp = max(time.perf_counter() - t0, 1e-3)
-    want = int(len(pilot) * min(15.0 / tp, 1e6))
-    sel = np.sort(perm[:max(len(pilot), min(want, dirs.shape[0]))])
-    t0 = time.perf_counter()
-    r = O.trace_uniform(n, box, obs, dirs[sel], chi_s, hi, lo, tv=tv, threads=cores)
-    t_trace = time.perf_counter() - t0
-    cross = int(r.ncross.sum())
-    del rp
-    log(f"oracle: tensor {t_tensor:.1f}s, {len(sel)} rays / {cross} crossings in {t_trace:.1f}s")
-    # GPU FP32 segment result for the same rays and segment (parity sample)
-    from paper_1601_02012_amd import api
-    g = api.Grid(phis[k], box)
-    t = api.TidalTensor(g, "fp32").build()
-    plan = api.Plan()
-    b = api.RayBundle(torch.as_tensor(dirs[sel]).cuda(), len(sel), 1, chi_s, hi, lo)
-    o = api.trace(plan, t, [b], obs, debug=True)
-    gk = o.kappa.double().cpu().numpy()
-    same = bool(np.array_equal(o.hash.cpu().numpy().view(np.uint64), r.hash))
-    err = np.abs(gk - r.kappa)
-    lim = np.maximum(1e-5 * np.abs(r.kappa), 1e-7)
-    t.close()
-    cb = {"value": cross / t_trace, "unit": "crossings/s", "cores": cores, "kind": "oracle",
-          "sample": f"{len(sel)} rays of the last chi segment ({cross} crossings), FP64 C oracle "
-                    f"with OpenMP; its {n}^3 vertex tensor took {t_tensor:.1f}s (not included)",
-          "tensor_build_s": t_tensor}
-    par = {"rays": len(sel), "crossing_hashes_equal": same,
-           "max_err_over_tol": float(np.max(err / lim))}
-    return cb, par
 
 
 if __name__ == "__main__":
