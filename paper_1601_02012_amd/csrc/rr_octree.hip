@@ -214,6 +214,7 @@ __global__ __launch_bounds__(256) void corner_kernel(Tree T, const Acc* __restri
       if (lv[o] == lc) oc = o;
     int lcc, IC[3];
     cell_coords(T, leaf[oc], lcc, IC);
+    const int period = T.n << lc;    // the coarse leaf may sit across the periodic face
     int cnt = 0;
     for (int sel = 0; sel < 8; ++sel) {
       int corner = 0;
@@ -227,6 +228,8 @@ __global__ __launch_bounds__(256) void corner_kernel(Tree T, const Acc* __restri
         } else {
           if (bit) skip = true;
           cb = (V[a] >> s) - IC[a];
+          cb = cb < 0 ? cb + period : (cb >= period ? cb - period : cb);
+          cb = cb > 1 ? 1 : cb;     // V lies on the leaf's boundary: 0 or 1
         }
         corner |= cb << a;
       }

@@ -185,3 +185,39 @@ def test_malformed_octrees_rejected(api):
     with pytest.raises(api.RRError) as e2:
         api.TidalTensor(g2, "fp64")
     assert e2.value.status == -5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_refinement_across_the_periodic_faces(api, oracle, plan, prec):
+    """Refined octs touching the box faces: corner tensors whose coarse
+    neighbours sit across the periodic boundary, and rays that wrap."""
+    import torch
+    rng = np.random.default_rng(41)
+    t = I.random_octree(8, 2, 0.3, rng)
+    base = t.cell_coord >> t.cell_level[:, None].astype(np.int64)
+    assert np.any(t.child_oct[(base == 0).any(axis=1) | (base == 7).any(axis=1)] >= 0)
+    box = 16.0
+    phi = _smooth_phi(t, box, rng)
+    dt = np.float64 if prec == "fp64" else np.float32
+    g = _gpu_octree_grid(api, t, phi, box, dt)
+    tt = api.TidalTensor(g, prec).build()
+    got = tt.to_torch().double().cpu().numpy().reshape(t.n_cells, 8, 6)
+    ot = _otree(oracle, t)
+    tc = oracle.centre_tensor_octree(ot, phi.astype(dt).astype(np.float64))
+    ref = oracle.corner_tensor_octree(ot, tc)
+    lv = t.leaves()
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    np.testing.assert_allclose(got[lv], ref[lv], rtol=0, atol=tol * np.abs(ref[lv]).max())
+    fov = math.radians(40.0)
+    dirs = I.fov_directions((-0.3, 0.4, 1.0), fov, fov, 16, 16)
+    obs = (0.3, 15.7, 0.1)
+    b = api.RayBundle(torch.as_tensor(dirs).cuda(), 16, 16, 50.0, 40.0, 0.0)
+    out = api.trace(plan, tt, [b], obs, debug=True)
+    r = oracle.trace_octree(ot, box, obs, dirs, 50.0, 40.0, 0.0, tc=tc)
+    assert np.array_equal(hashes_u64(out.hash), r.hash)
+    k = out.kappa.double().cpu().numpy()
+    if prec == "fp64":
+        np.testing.assert_allclose(k, r.kappa, rtol=0, atol=1e-11 * np.abs(r.kappa).max())
+    else:
+        ok, worst = kappa_tolerance_ok(k, r.kappa)
+        assert ok, worst
