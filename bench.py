@@ -114,7 +114,7 @@ def lightcone_leg(args, api, I, torch, dev):
             o = api.trace(plan, t, bundles[k], obs, debug=True, persistent=0)
             total_cross += int(o.count.sum().item())
             del o
-            if not args.no_tune:
+            if args.tune_lightcone:
                 shapes.append(plan.autotune(t, bundles[k], obs))
         log(f"{prec}: {total_cross:.4e} crossings per light cone; tuned shapes "
             f"{sorted(set((s['persistent'], s['block'], s['waves_per_cu']) for s in shapes))}")
@@ -129,7 +129,7 @@ def lightcone_leg(args, api, I, torch, dev):
                 t.build(grids[k])
                 ev[k][1].record(stream)
                 api.trace(plan, t, bundles[k], obs, kappa=kap, kappa_comp=comp, status=st,
-                          persistent=-1)
+                          persistent=-1 if args.tune_lightcone else 0)
                 ev[k][2].record(stream)
 
         step_ms = timed(step, args.steps, args.warmup, f"light cone {prec}")
@@ -305,7 +305,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the AMR leg's autotuning")
+    ap.add_argument("--tune-lightcone", action="store_true",
+                    help="autotune the light-cone launch shape per segment (default: one "
+                         "wavefront per tile, 256-thread workgroups)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", action="store_true",
                     help="short light-cone-only run for profilers (no FP64, CPU or AMR legs)")
