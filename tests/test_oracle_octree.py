@@ -151,3 +151,61 @@ def test_P2_quadratic_on_octree_refinement_invariant(oracle, seed):
     qv = np.trace(M) - np.einsum("ri,ij,rj->r", dirs, M, dirs)
     expect = qv * ((chis * (hi ** 2 - lo ** 2) / 2 - (hi ** 3 - lo ** 3) / 3) / chis)
     np.testing.assert_allclose(r.kappa, expect, rtol=1e-11)
+
+
+def test_P8_face_centre_hanging_vertex(oracle):
+    """A vertex in the middle of a coarse face takes the mean of the face's
+    four coarse corner values (Sec. III F, text after Eq. rhoV_1)."""
+    n = 4
+    t = I.build_octree(n, 1, lambda l, c: np.all(c == np.array([1, 1, 1]), axis=1))
+    ot = _otree(oracle, t)
+    rng = np.random.default_rng(6)
+    tc = rng.normal(size=(t.n_cells, 6))
+    cv = oracle.corner_tensor_octree(ot, tc)
+    # child 0 (level-1 coords (2,2,2)) has corner 3 = (3,3,2): the centre of the
+    # refined cell's lower-z face, i.e. of the upper face of coarse cell (1,1,0)
+    base = lambda i, j, k: (k * n + j) * n + i
+    corner_val = lambda cell, v: cv[cell, v]
+    c0 = base(1, 1, 0)
+    face = [corner_val(c0, v) for v in (4, 5, 6, 7)]      # upper-z face of the coarse cell
+    np.testing.assert_allclose(cv[n ** 3 + 0, 3], np.mean(face, axis=0), rtol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_P17_cubic_potential_exact_centre_tensor_on_octree(oracle, seed):
+    """Cubic Phi on a multi-level octree: the level-l stencil is exact for
+    cubics, and the coarse-level fallback (trilinear 3/4-1/4 interpolation of
+    a linear tensor field) is exact too, so every interior cell's centre
+    tensor equals the analytic Hessian at its centre (Sec. IV C, option 2)."""
+    rng = np.random.default_rng(200 + seed)
+    n, L = 12, 12.0
+    t = I.random_octree(n, 3, 0.3, rng, region=(3.0, 9.0))
+    ot = _otree(oracle, t)
+    M = rng.normal(size=(3, 3)); M = M + M.T
+    Ct = rng.normal(size=(3, 3, 3)) * 0.1
+    C = sum(np.transpose(Ct, p) for p in [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]) / 6
+    x = t.centres(L)
+    phi = 0.5 * np.einsum("ci,ij,cj->c", x, M, x) + np.einsum("abc,ia,ib,ic->i", C, x, x, x) / 6
+    tc = oracle.centre_tensor_octree(ot, phi)
+    H = M[None] + np.einsum("abc,ic->iab", C, x)
+    ref = np.stack([H[:, 0, 0], H[:, 1, 1], H[:, 2, 2], H[:, 0, 1], H[:, 0, 2], H[:, 1, 2]], -1)
+    h = (L / n) / (2.0 ** t.cell_level)
+    # interior: the cell and its stencil (plus the coarse fallback cells) stay away from the faces
+    inside = np.all((x > 2.5 * (L / n)) & (x < L - 2.5 * (L / n)), axis=1)
+    fallback_cells = 0
+    for lvl in range(1, t.max_level + 1):
+        sel = inside & (t.cell_level == lvl)
+        np.testing.assert_allclose(tc[sel], ref[sel], rtol=0, atol=1e-9 * np.abs(ref).max())
+        # cells of this level with a face neighbour missing at their level take the fallback
+        nl = n << lvl
+        key = lambda c: (c[:, 2] * nl + c[:, 1]) * nl + c[:, 0]
+        have = set(key(t.cell_coord[t.cell_level == lvl]).tolist())
+        cc = t.cell_coord[sel]
+        for a in range(3):
+            for s_ in (-1, 1):
+                nb_ = cc.copy()
+                nb_[:, a] += s_
+                fallback_cells += sum(k not in have for k in key(nb_).tolist())
+    np.testing.assert_allclose(tc[inside & (t.cell_level == 0)], ref[inside & (t.cell_level == 0)],
+                               rtol=0, atol=1e-9 * np.abs(ref).max())
+    assert fallback_cells > 0
