@@ -36,6 +36,7 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_CROSSING = {"fp32": 96, "fp64": 192}     # 4 new corners x 6 components
 BYTES_PER_VERTEX = {"fp32": 4 + 24, "fp64": 4 + 48}  # potential in, 6 components out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_traffic.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_counters.md")
 MARCH_SOURCES = ["paper_1601_02012_amd/csrc/rr_march_uniform.hip",
                  "paper_1601_02012_amd/csrc/rr_ray.hpp",
                  "paper_1601_02012_amd/csrc/rr_internal.hpp"]
@@ -53,17 +54,22 @@ def march_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per march launch from the committed rocprofv3 counter summary,
-    if it was taken on the current march source (else None)."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    txt = open(TRAFFIC_FILE).read()
-    m_src = re.search(r"march_source_sha256_16:\s*([0-9a-f]+)", txt)
-    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_src or not m_b or m_src.group(1) != march_source_hash():
-        return None
-    return float(m_b.group(1))
+def profile_figures():
+    """Figures from the committed rocprofv3 summaries (HBM bytes per march launch, L2 hit
+    fraction, VALU busy fraction, VALU instructions per crossing), each kept only if the
+    summary was taken on the current march source."""
+    src = march_source_hash()
+    out = {}
+    for path in (TRAFFIC_FILE, COUNTERS_FILE):
+        if not os.path.exists(path):
+            continue
+        txt = open(path).read()
+        m_src = re.search(r"march_source_sha256_16:\s*([0-9a-f]+)", txt)
+        if not m_src or m_src.group(1) != src:
+            continue
+        for key, val in re.findall(r"^(\w+):\s*([0-9.eE+-]+)\s*$", txt, re.M):
+            out[key] = float(val)
+    return out
 
 
 def timed(fn, steps, warmup, label):
@@ -335,7 +341,8 @@ def main():
     march_launch_ms = r32["march_ms"] / nseg
     cross_per_launch = r32["cross"] / nseg
     achieved = BYTES_PER_CROSSING["fp32"] * cross_per_launch / (march_launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    prof = profile_figures()
+    traffic = prof.get("hbm_bytes_per_launch")
     out = {
         "metric": "ray-cell crossings/sec and HBM GB/s, FP32-comp vs FP64 at 1e-5 rel kappa err",
         "value": value,
@@ -358,6 +365,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
+                                     "copy-calibrated)",
+                     "algorithmic_bytes_per_launch": BYTES_PER_CROSSING["fp32"] * cross_per_launch,
+                     "measured_hbm_gbs": (traffic / (march_launch_ms * 1e-3) / 1e9
+                                          if traffic else None),
+                     "l2_hit_frac": prof.get("march_l2_hit_frac"),
+                     "valu_busy_frac": prof.get("march_valu_busy_frac"),
+                     "valu_insts_per_crossing": prof.get("march_valu_insts_per_crossing"),
                      "kernel": "march_uniform (FP32-Kahan)",
                      "bytes_per_crossing": BYTES_PER_CROSSING["fp32"],
                      "launch_ms": march_launch_ms, "crossings_per_launch": cross_per_launch,
