@@ -134,6 +134,18 @@ rr_status rr_tensor_destroy(rr_tensor t);
  * step).  Asynchronous on s; no allocation. */
 rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s);
 
+/* The same tensor, built only on the vertices of the periodic box
+ * [lo, lo + size) (vertex lattice indices; lo may lie outside [0, n) and the
+ * box wraps; 0 <= size[a] <= n).  Vertices outside the box keep the values
+ * of earlier builds.  The rays of one N-body step only read the vertices
+ * around their chi segment (rr_rays_vertex_box), and the tensor work can be
+ * limited to them (Sec. III F: the interpolation is worth doing only where
+ * rays need it).  Uniform grids only (RR_ERR_UNSUPPORTED otherwise); open
+ * grids take boxes inside [0, n) (RR_ERR_DOMAIN).  Asynchronous on s; no
+ * allocation. */
+rr_status rr_build_tidal_tensor_box(rr_tensor t, const rr_field_desc* f, const int32_t lo[3],
+                                    const int32_t size[3], rr_stream s);
+
 /* Device layout of a built tensor, for inspection.  Uniform: *data holds
  * n_base^3 records of `stride` bytes, components first (float or double by
  * precision).  Octree: n_cells records of 8 corners x 6 components
@@ -198,6 +210,18 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp,
                         const rr_bundle* bundles /* host */, int32_t n_bundles, void* kappa,
                         float* kappa_comp, int32_t* ray_status, rr_stream s);
 
+/* The vertex box (lo, size as taken by rr_build_tidal_tensor_box) that
+ * contains every vertex the rays of these bundles read between their chi_lo
+ * and chi_hi: the lattice bounds of the rays' end points, widened by the
+ * slab rule and the cells' upper corners, clipped to the whole axis (or, on
+ * open grids, to [0, n)).  An empty bundle set gives size 0.  Runs a small
+ * reduction kernel on s and waits for it (synchronous; not inside a
+ * capture); uploads the bundle table like rr_trace_rays.  Uniform grids
+ * only. */
+rr_status rr_rays_vertex_box(rr_plan p, rr_tensor t, const rr_trace_params* tp,
+                             const rr_bundle* bundles, int32_t n_bundles, int32_t lo[3],
+                             int32_t size[3], rr_stream s);
+
 /* Tune the launch shape for this bundle set: times one-wavefront-per-tile
  * launches (64- and 256-thread workgroups) and persistent workgroups fed by
  * the device queue (8, 16 or 32 wavefronts per compute unit) on scratch
@@ -216,9 +240,11 @@ rr_status rr_plan_tuned_shape(rr_plan p, const rr_bundle* bundles, int32_t n_bun
  * FP32, same layout as f->values).  kappa is linear in Phi (straight rays,
  * Born approximation, Sec. IV A), and the result is the exact transpose of
  * the forward chain (per-cell integral, vertex mean, finite differences),
- * accumulated with FP32 atomics (order-dependent rounding).  Uses the
- * tensor's storage as scratch: rebuild the tensor before the next trace.
- * Octree fields return RR_ERR_UNSUPPORTED. */
+ * accumulated with FP32 atomics (order-dependent rounding).  The first call
+ * on a tensor allocates a workspace of 8 FP32 values per vertex (32 B x n^3),
+ * kept with the tensor until rr_tensor_destroy; the tensor's own values are
+ * not modified.  Needs the FP32 Kahan precision, a periodic uniform field and
+ * RR_Q_KAPPA; anything else returns RR_ERR_UNSUPPORTED. */
 rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
                                 const rr_trace_params* tp, const rr_bundle* bundles,
                                 int32_t n_bundles, const float* dl_dkappa, float* dl_dphi,

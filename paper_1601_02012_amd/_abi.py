@@ -52,6 +52,8 @@ SIGNATURES = [
     ("rr_tensor_create", _i32, [C.POINTER(FieldDesc), _i32, C.POINTER(_vp)]),
     ("rr_tensor_destroy", _i32, [_vp]),
     ("rr_build_tidal_tensor", _i32, [_vp, C.POINTER(FieldDesc), _vp]),
+    ("rr_build_tidal_tensor_box", _i32, [_vp, C.POINTER(FieldDesc), C.POINTER(_i32),
+                                         C.POINTER(_i32), _vp]),
     ("rr_tensor_layout", _i32, [_vp, C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_i32),
                                 C.POINTER(_i32)]),
     ("rr_plan_create", _i32, [C.POINTER(_vp)]),
@@ -60,6 +62,8 @@ SIGNATURES = [
                              _vp, _vp]),
     ("rr_trace_rays_adjoint", _i32, [_vp, _vp, C.POINTER(FieldDesc), C.POINTER(TraceParams),
                                      C.POINTER(Bundle), _i32, _vp, _vp, _vp]),
+    ("rr_rays_vertex_box", _i32, [_vp, _vp, C.POINTER(TraceParams), C.POINTER(Bundle), _i32,
+                                  C.POINTER(_i32), C.POINTER(_i32), _vp]),
     ("rr_plan_autotune", _i32, [_vp, _vp, C.POINTER(TraceParams), C.POINTER(Bundle), _i32, _vp]),
     ("rr_plan_tuned_shape", _i32, [_vp, C.POINTER(Bundle), _i32, C.POINTER(_i32), C.POINTER(_i32),
                                    C.POINTER(_i32), C.POINTER(C.c_float)]),

@@ -99,6 +99,18 @@ class TidalTensor:
                 _lib.rr_build_tidal_tensor(self.handle, C.byref(d), _stream(stream)))
         return self
 
+    def build_box(self, lo, size, grid: Optional[Grid] = None, stream=None) -> "TidalTensor":
+        """rr_build_tidal_tensor_box: rebuild only the vertices of the periodic box."""
+        g = grid if grid is not None else self.grid
+        self.grid = g
+        d = g.desc()
+        lo_a = (C.c_int32 * 3)(*[int(x) for x in lo])
+        sz_a = (C.c_int32 * 3)(*[int(x) for x in size])
+        A.check("rr_build_tidal_tensor_box",
+                _lib.rr_build_tidal_tensor_box(self.handle, C.byref(d), lo_a, sz_a,
+                                               _stream(stream)))
+        return self
+
     def layout(self):
         p = C.c_void_p()
         n = C.c_int64()
@@ -165,6 +177,17 @@ class Plan:
                                          C.byref(blk), C.byref(wpc), C.byref(ms)))
         return {"persistent": pers.value, "block": blk.value, "waves_per_cu": wpc.value,
                 "ms": ms.value}
+
+    def vertex_box(self, tensor: "TidalTensor", bundles, observer, stream=None):
+        """rr_rays_vertex_box: (lo, size) of the vertices these bundles' rays read."""
+        tp = _params(observer, tensor.precision)
+        arr = _bundle_array(bundles)
+        lo = (C.c_int32 * 3)()
+        size = (C.c_int32 * 3)()
+        A.check("rr_rays_vertex_box",
+                _lib.rr_rays_vertex_box(self.handle, tensor.handle, C.byref(tp), arr, len(bundles),
+                                        lo, size, _stream(stream)))
+        return tuple(lo), tuple(size)
 
     def graph_begin(self, stream=None):
         A.check("rr_graph_begin", _lib.rr_graph_begin(self.handle, _stream(stream)))

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -78,7 +79,7 @@ struct TunedShape {
 }  // namespace
 
 struct rr_plan_s {
-  unsigned long long* queue = nullptr;
+  unsigned long long* queue = nullptr;   // work queue counter; bytes 64.. hold ray bounds
   std::vector<CachedTable> tables;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -192,15 +193,42 @@ rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s
   if (f->kind != t->kind || f->n_base != t->n || f->boundary != t->boundary)
     return fail(RR_ERR_INVALID_ARG, "field does not match the grid the tensor was created for");
   if (f->kind == RR_GRID_UNIFORM) {
+    const int lo[3] = {0, 0, 0}, size[3] = {f->n_base, f->n_base, f->n_base};
     RR_HIP(rr::launch_vertex_tensor_uniform(t->precision, f->dtype, f->n_base,
-                                            f->boundary == RR_BOUNDARY_OPEN, f->values, t->data,
-                                            (hipStream_t)s),
+                                            f->boundary == RR_BOUNDARY_OPEN, lo, size, f->values,
+                                            t->data, (hipStream_t)s),
            "vertex tensor launch");
     return RR_OK;
   }
   if (f->n_cells != t->oct->n_cells || f->child_oct != t->oct->child_oct_dev)
     return fail(RR_ERR_INVALID_ARG, "octree does not match the one the tensor was created for");
   RR_HIP(t->oct->build(f->values, f->dtype, (hipStream_t)s), "octree tensor launch");
+  return RR_OK;
+}
+
+rr_status rr_build_tidal_tensor_box(rr_tensor t, const rr_field_desc* f, const int32_t lo[3],
+                                     const int32_t size[3], rr_stream s) {
+  if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  if (!lo || !size) return fail(RR_ERR_INVALID_ARG, "box pointers are NULL");
+  rr_status st = validate_field(f);
+  if (st != RR_OK) return st;
+  if (f->kind != RR_GRID_UNIFORM || t->kind != RR_GRID_UNIFORM)
+    return fail(RR_ERR_UNSUPPORTED, "box builds are for uniform grids");
+  if (f->n_base != t->n || f->boundary != t->boundary)
+    return fail(RR_ERR_INVALID_ARG, "field does not match the grid the tensor was created for");
+  const int n = f->n_base;
+  for (int a = 0; a < 3; ++a) {
+    if (size[a] < 0 || size[a] > n)
+      return fail(RR_ERR_INVALID_ARG, "box size %d on axis %d outside [0, %d]", size[a], a, n);
+    if (std::abs((int64_t)lo[a]) > (1ll << 30))
+      return fail(RR_ERR_INVALID_ARG, "box origin %d on axis %d is too far out", lo[a], a);
+    if (f->boundary == RR_BOUNDARY_OPEN && (lo[a] < 0 || lo[a] + size[a] > n))
+      return fail(RR_ERR_DOMAIN, "open grids take boxes inside [0, n)");
+  }
+  RR_HIP(rr::launch_vertex_tensor_uniform(t->precision, f->dtype, n,
+                                          f->boundary == RR_BOUNDARY_OPEN, lo, size, f->values,
+                                          t->data, (hipStream_t)s),
+         "vertex tensor launch");
   return RR_OK;
 }
 
@@ -390,6 +418,56 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp, const
   }
   return launch_trace(p, t, tp, bundles, n_bundles, kappa, kappa_comp, ray_status, hs, persistent,
                       block, waves_per_cu);
+}
+
+rr_status rr_rays_vertex_box(rr_plan p, rr_tensor t, const rr_trace_params* tp,
+                             const rr_bundle* bundles, int32_t n_bundles, int32_t lo[3],
+                             int32_t size[3], rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  if (!lo || !size) return fail(RR_ERR_INVALID_ARG, "box pointers are NULL");
+  rr_status st = validate_trace(t, tp, bundles, n_bundles);
+  if (st != RR_OK) return st;
+  if (t->kind != RR_GRID_UNIFORM) return fail(RR_ERR_UNSUPPORTED, "box builds are for uniform grids");
+  const hipStream_t hs = (hipStream_t)s;
+  if (capturing(hs)) return fail(RR_ERR_CAPACITY, "the ray box is computed outside captures");
+  const CachedTable* tab = nullptr;
+  st = get_table(p, t, bundles, n_bundles, 0, hs, &tab);
+  if (st != RR_OK) return st;
+  int* dev = reinterpret_cast<int*>(reinterpret_cast<char*>(p->queue) + 64);
+  int host[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
+  RR_HIP(hipMemcpyAsync(dev, host, sizeof(host), hipMemcpyHostToDevice, hs), "bounds init");
+  rr::TraceArgs a{};
+  a.bundles = tab->dev;
+  a.n_bundles = n_bundles;
+  a.n_tiles = tab->n_tiles;
+  const double h0 = t->box / (double)t->n;
+  for (int k = 0; k < 3; ++k) a.o[k] = tp->observer[k] / h0;
+  a.n = t->n;
+  RR_HIP(rr::launch_ray_bounds(a, dev, hs), "ray bounds launch");
+  RR_HIP(hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, hs), "bounds read");
+  RR_HIP(hipStreamSynchronize(hs), "bounds sync");
+  const int n = t->n;
+  for (int k = 0; k < 3; ++k) {
+    if (host[k] > host[3 + k]) {   // no traced ray
+      lo[k] = 0;
+      size[k] = 0;
+      continue;
+    }
+    // cells of the walk: one slab beyond the end points either way (the slab
+    // rule at a plane); vertices: their lower and upper corners, plus one
+    // layer of margin
+    const int64_t a0 = (int64_t)host[k] - 2, a1 = (int64_t)host[3 + k] + 3;   // [a0, a1)
+    if (a1 - a0 >= n || t->boundary == RR_BOUNDARY_OPEN) {
+      const int64_t c0 = t->boundary == RR_BOUNDARY_OPEN ? std::max<int64_t>(a0, 0) : 0;
+      const int64_t c1 = t->boundary == RR_BOUNDARY_OPEN ? std::min<int64_t>(a1, n) : n;
+      lo[k] = (int32_t)c0;
+      size[k] = (int32_t)std::max<int64_t>(c1 - c0, 0);
+    } else {
+      lo[k] = (int32_t)a0;
+      size[k] = (int32_t)(a1 - a0);
+    }
+  }
+  return RR_OK;
 }
 
 rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,

@@ -57,8 +57,13 @@ struct VertexRecord<double> {
 };
 
 // host launchers (defined in the .hip files)
-hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int open,
-                                        const void* phi, void* tv, hipStream_t s);
+hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int open, const int* lo,
+                                        const int* size, const void* phi, void* tv,
+                                        hipStream_t s);
+// min / max over the rays of the floor of their lattice coordinates at both
+// ends of their chi windows: out[0..2] min, out[3..5] max (atomics; the
+// caller initialises out)
+hipError_t launch_ray_bounds(const TraceArgs& a, int* out, hipStream_t s);
 hipError_t launch_march_uniform(int precision, const void* tv, const TraceArgs& a, int persistent,
                                 int block, int grid_waves, hipStream_t s);
 hipError_t launch_queue_reset(unsigned long long* q, hipStream_t s);

@@ -9,6 +9,8 @@
 // Tiles are either mapped one per wavefront from the grid (XCD-striped so a
 // chiplet's L2 sees a contiguous part of the sky) or pulled from a device
 // queue by persistent workgroups.
+#include <climits>
+
 #include "rr_ray.hpp"
 
 namespace rr {
@@ -19,29 +21,70 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-template <typename R>
-__device__ __forceinline__ void load_vertex(const R* __restrict__ tv, uint64_t v, R* t);
-
-template <>
-__device__ __forceinline__ void load_vertex<float>(const float* __restrict__ tv, uint64_t v,
-                                                   float* t) {
-  const float2* p = reinterpret_cast<const float2*>(tv + v * 6);
-  const float2 a = p[0], b = p[1], c = p[2];
-  t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y; t[4] = c.x; t[5] = c.y;
+// Vertex record at byte offset `off` of the tensor (6 components: three
+// 8-byte accesses in FP32, three 16-byte accesses in FP64).  A 32-bit offset
+// lets the load take the array base from scalar registers.
+template <typename R, typename Off>
+__device__ __forceinline__ void load_vertex(const R* __restrict__ tv, Off off, R* t) {
+  const char* b = reinterpret_cast<const char*>(tv) + (uint64_t)off;
+  if constexpr (sizeof(R) == 4) {
+    const float2* p = reinterpret_cast<const float2*>(b);
+    const float2 x = p[0], y = p[1], z = p[2];
+    t[0] = x.x; t[1] = x.y; t[2] = y.x; t[3] = y.y; t[4] = z.x; t[5] = z.y;
+  } else {
+    const double2* p = reinterpret_cast<const double2*>(b);
+    const double2 x = p[0], y = p[1], z = p[2];
+    t[0] = x.x; t[1] = x.y; t[2] = y.x; t[3] = y.y; t[4] = z.x; t[5] = z.y;
+  }
 }
-template <>
-__device__ __forceinline__ void load_vertex<double>(const double* __restrict__ tv, uint64_t v,
-                                                    double* t) {
-  const double2* p = reinterpret_cast<const double2*>(tv + v * 6);
-  const double2 a = p[0], b = p[1], c = p[2];
-  t[0] = a.x; t[1] = a.y; t[2] = b.x; t[3] = b.y; t[4] = c.x; t[5] = c.y;
+
+// Q_v = P : T_v for the vertex record at byte offset off.
+template <typename R, typename Off>
+__device__ __forceinline__ R project(const R* __restrict__ tv, Off off, const R* P) {
+  R t[6];
+  load_vertex<R, Off>(tv, off, t);
+  R acc = P[0] * t[0];
+#pragma unroll
+  for (int c = 1; c < 6; ++c) acc = fma(P[c], t[c], acc);
+  return acc;
 }
 
-// One ray.  Per axis the lane keeps, in FP64, the coordinate of the exit
-// plane, its crossing parameter and the local-coordinate offset o~ - m; the
-// cell's wrapped indices are kept as integer offsets into the vertex array, so
-// a crossing costs no integer division and no int->float conversion.
-template <typename R, bool kDebug, typename Idx>
+// All eight corners (c = b0 + 2 b1 + 4 b2), loaded in two halves so that at
+// most four vertex records are in flight: this path runs only at the start of
+// a ray and after edge or vertex crossings, and must not set the register
+// budget of the whole loop.
+template <typename R, typename Off>
+__device__ __forceinline__ void load_corners(const R* __restrict__ tv, Off base, const Off* dX,
+                                             const R* P, R* q) {
+  const Off v2 = base + dX[1];
+  q[0] = project<R, Off>(tv, base, P);
+  q[1] = project<R, Off>(tv, base + dX[0], P);
+  q[2] = project<R, Off>(tv, v2, P);
+  q[3] = project<R, Off>(tv, v2 + dX[0], P);
+  __builtin_amdgcn_sched_barrier(0);
+  const Off v4 = base + dX[2];
+  const Off v6 = v4 + dX[1];
+  q[4] = project<R, Off>(tv, v4, P);
+  q[5] = project<R, Off>(tv, v4 + dX[0], P);
+  q[6] = project<R, Off>(tv, v6, P);
+  q[7] = project<R, Off>(tv, v6 + dX[0], P);
+}
+
+// One ray, in the ray's own frame: along each axis, corner bit 0 is the
+// vertex layer of the face the ray enters through and bit 1 the layer of the
+// face it leaves through, and the local coordinate f runs from 0 (entry face)
+// to 1 (exit face).  A crossing of one face then keeps the four projected
+// corner values of that face (they become the entry face of the next cell)
+// and loads only the four of the new exit face; a crossing through an edge or
+// a vertex reloads all eight.
+//
+// Per axis the lane keeps, in FP64, the crossing parameter of the exit plane
+// (f = 1 - |n_a| (chi - t_exit) inside the slab) and its reciprocal
+// direction, and as integers the exit plane's lattice coordinate and the
+// wrapped index of the exit vertex layer; the cell's entry corner is one byte
+// offset into the vertex array (32 bit when the tensor is below 4 GiB), with
+// per-axis steps to the exit layer (modular arithmetic).
+template <typename R, bool kDebug, typename Off>
 __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const DevBundle& B,
                           int64_t ray) {
   const int64_t out = B.ray_offset + ray;
@@ -53,36 +96,56 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     if (a.status) a.status[out] = RR_RAY_BAD_DIRECTION;
     return;
   }
-  double Pd[6];
-  projection(a.quantity, d[0], d[1], d[2], Pd);
   R P[6];
+  {
+    double Pd[6];
+    projection(a.quantity, d[0], d[1], d[2], Pd);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) P[c] = (R)Pd[c];
+    for (int c = 0; c < 6; ++c) P[c] = (R)Pd[c];
+  }
 
   const int n = a.n;
-  const Idx nI = (Idx)n, nnI = (Idx)n * (Idx)n;
+  constexpr Off kRec = (Off)(6 * sizeof(R));  // bytes per vertex record
+  const Off stride[3] = {kRec, kRec * (Off)n, kRec * (Off)n * (Off)n};
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
-  double r[3], pe[3], te[3], cpos[3], sgn[3];
-  int m[3], w[3];
-  Idx off0[3], off1[3];           // wrapped offsets of the cell's lower / upper vertex layer
-  const Idx stride[3] = {(Idx)1, nI, nnI};
+  double r[3], te[3];
+  R absd[3];         // f(chi) = 1 - absd (chi - t_exit)
+  int px[3];         // lattice coordinate of the exit plane (unwrapped, replicated box)
+  int xl[3];         // exit vertex layer, wrapped into [0, n)
+  Off base = 0;      // byte offset of the corner on all three entry layers
+  Off dX[3];         // byte step from the entry to the exit layer
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     r[k] = (d[k] != 0.0) ? 1.0 / d[k] : 0.0;
-    m[k] = start_slab(a.o[k], d[k], r[k], chiA, 1.0);
-    sgn[k] = d[k] > 0.0 ? -1.0 : 1.0;            // step of m along the march
-    pe[k] = (double)(d[k] > 0.0 ? m[k] : m[k] + 1);
-    te[k] = d[k] != 0.0 ? tplane(pe[k], a.o[k], r[k]) : -__builtin_inf();
-    cpos[k] = a.o[k] - (double)m[k];
-    int ww = m[k] % n;
-    w[k] = ww < 0 ? ww + n : ww;
-    off0[k] = (Idx)w[k] * stride[k];
-    off1[k] = (Idx)(w[k] + 1 == n ? 0 : w[k] + 1) * stride[k];
+    const int m = start_slab(a.o[k], d[k], r[k], chiA, 1.0);
+    // n_a > 0: the march runs down the lattice, leaving through plane m;
+    // otherwise up, leaving through plane m + 1 (never reached if n_a = 0)
+    px[k] = d[k] > 0.0 ? m : m + 1;
+    if (d[k] != 0.0) {
+      te[k] = tplane((double)px[k], a.o[k], r[k]);
+      absd[k] = (R)fabs(d[k]);
+    } else {
+      // never crossed: a slope of 1e-30 with an exit parameter (1 - f) 1e30
+      // below reproduces the fixed coordinate f = o~ - m to rounding, and the
+      // parameter is never the largest (chi_lo >= 0)
+      te[k] = -(1.0 - (a.o[k] - (double)m)) * 1e30;
+      absd[k] = (R)1e-30;
+    }
+    int lm = m % n;
+    lm = lm < 0 ? lm + n : lm;                       // layer of plane m
+    const int lp = lm + 1 == n ? 0 : lm + 1;         // layer of plane m + 1
+    const int el = d[k] > 0.0 ? lp : lm;
+    xl[k] = d[k] > 0.0 ? lm : lp;
+    base += (Off)el * stride[k];
+    dX[k] = (Off)xl[k] * stride[k] - (Off)el * stride[k];
   }
-  R uA[3];
+  R fA[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) uA[k] = (R)fma(chiA, d[k], cpos[k]);
+  for (int k = 0; k < 3; ++k) fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
+
+  R q[8];  // corner values, corner c = b0 + 2 b1 + 4 b2 in the ray frame
+  load_corners<R, Off>(tv, base, dX, P, q);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
@@ -100,10 +163,17 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
 
   for (;;) {
-    if (a.open && (m[0] < 2 || m[1] < 2 || m[2] < 2 || m[0] > n - 3 || m[1] > n - 3 ||
-                   m[2] > n - 3)) {
-      st = RR_RAY_OUT_OF_DOMAIN;
-      break;
+    if (a.open) {
+      bool outside = false;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int m = r[k] > 0.0 ? px[k] : px[k] - 1;
+        outside |= m < 2 || m > n - 3;
+      }
+      if (outside) {
+        st = RR_RAY_OUT_OF_DOMAIN;
+        break;
+      }
     }
     if (count >= maxc) {
       st = RR_RAY_MAX_STEPS;
@@ -118,39 +188,23 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
 #pragma unroll
     for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
 
-    // the eight corners (v = ix + 2 iy + 4 iz), projected on the ray's P
-    R q[8];
-    {
-      const Idx zy00 = off0[2] + off0[1], zy01 = off0[2] + off1[1];
-      const Idx zy10 = off1[2] + off0[1], zy11 = off1[2] + off1[1];
-      const Idx vid[8] = {zy00 + off0[0], zy00 + off1[0], zy01 + off0[0], zy01 + off1[0],
-                          zy10 + off0[0], zy10 + off1[0], zy11 + off0[0], zy11 + off1[0]};
+    // local coordinates of the exit point; exactly 1 on the crossed faces
+    R fB[3];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        R t[6];
-        load_vertex<R>(tv, (uint64_t)vid[v], t);
-        R acc = P[0] * t[0];
-#pragma unroll
-        for (int c = 1; c < 6; ++c) acc = fma(P[c], t[c], acc);
-        q[v] = acc;
-      }
-    }
-    // local coordinates of the exit point; exact on the crossed faces
-    R uB[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const R face = d[k] > 0.0 ? (R)0 : (R)1;
-      uB[k] = stepped[k] ? face : (R)fma(chiB, d[k], cpos[k]);
-    }
+    for (int k = 0; k < 3; ++k) fB[k] = (R)1 - absd[k] * (R)(chiB - te[k]);
     const R L = (R)(chiA - chiB);
-    const R ic = cell_integral<R>(q, uA, uB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+    const R ic = cell_integral<R>(q, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
     if constexpr (sizeof(R) == 4) {
       kahan_add(sum, comp, ic);
     } else {
       sum += ic;
     }
     if constexpr (kDebug) {
-      const int64_t cell = (int64_t)(off0[2] + off0[1] + off0[0]);
+      // cell id = vertex id of its lower corner: the exit layer where n_a > 0
+      Off low = base;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) low += r[k] > 0.0 ? dX[k] : (Off)0;
+      const int64_t cell = (int64_t)(low / kRec);
       if (a.hash) hv = fnv_piece(hv, cell, chiA, chiB);
       if (a.log && count < a.log_stride) {
         LogRecord* L0 = reinterpret_cast<LogRecord*>(a.log) + out * a.log_stride + count;
@@ -161,24 +215,52 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     }
     ++count;
     if (chiB == lo) break;
-    // step every axis whose exit plane is at chi_B; the entry point of the
-    // next cell is the exit point of this one
+    // step every axis whose exit plane is at chi_B: the exit layer becomes
+    // the entry layer, the next layer along the march the exit layer
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uA[k] = uB[k];
+      fA[k] = fB[k];
       if (stepped[k]) {
-        pe[k] += sgn[k];
-        te[k] = tplane(pe[k], a.o[k], r[k]);
-        cpos[k] -= sgn[k];
-        uA[k] = (R)1 - uB[k];
-        const int s = d[k] > 0.0 ? -1 : 1;
-        m[k] += s;
-        int ww = w[k] + s;
-        ww = ww < 0 ? ww + n : (ww >= n ? ww - n : ww);
-        w[k] = ww;
-        off0[k] = (Idx)ww * stride[k];
-        off1[k] = (Idx)(ww + 1 == n ? 0 : ww + 1) * stride[k];
+        fA[k] = (R)0;
+        const bool down = r[k] > 0.0;
+        px[k] += down ? -1 : 1;
+        te[k] = tplane((double)px[k], a.o[k], r[k]);
+        base += dX[k];
+        const Off wrapstep = (Off)(n - 1) * stride[k];
+        if (down) {
+          const bool wrap = xl[k] == 0;
+          xl[k] = wrap ? n - 1 : xl[k] - 1;
+          dX[k] = wrap ? wrapstep : (Off)0 - stride[k];
+        } else {
+          const bool wrap = xl[k] == n - 1;
+          xl[k] = wrap ? 0 : xl[k] + 1;
+          dX[k] = wrap ? (Off)0 - wrapstep : stride[k];
+        }
       }
+    }
+    if ((int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1) {
+      // one face crossed (axis k): keep its four values, load the new exit face,
+      // whose corners F_j (j = i_a + 2 i_b over the two other axes a < b)
+      const bool k0 = stepped[0], k1 = stepped[1];
+      const Off dk = k0 ? dX[0] : (k1 ? dX[1] : dX[2]);
+      const Off da = k0 ? dX[1] : dX[0];
+      const Off db = k0 || k1 ? dX[2] : dX[1];
+      const Off w0 = base + dk, w1 = w0 + da;
+      const R F0 = project<R, Off>(tv, w0, P);
+      const R F1 = project<R, Off>(tv, w1, P);
+      const R F2 = project<R, Off>(tv, w0 + db, P);
+      const R F3 = project<R, Off>(tv, w1 + db, P);
+      const R n0 = k0 ? q[1] : (k1 ? q[2] : q[4]);
+      const R n1 = k0 ? F0 : (k1 ? q[3] : q[5]);
+      const R n2 = k0 ? q[3] : (k1 ? F0 : q[6]);
+      const R n3 = k0 || k1 ? F1 : q[7];
+      const R n4 = k0 ? q[5] : (k1 ? q[6] : F0);
+      const R n5 = k0 ? F2 : (k1 ? q[7] : F1);
+      const R n6 = k0 ? q[7] : F2;
+      q[0] = n0; q[1] = n1; q[2] = n2; q[3] = n3;
+      q[4] = n4; q[5] = n5; q[6] = n6; q[7] = F3;
+    } else {
+      load_corners<R, Off>(tv, base, dX, P, q);
     }
     chiA = chiB;
   }
@@ -196,7 +278,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   }
 }
 
-template <typename R, bool kDebug, typename Idx>
+template <typename R, bool kDebug, typename Off>
 __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -204,13 +286,17 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Idx>(tv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Off>(tv, a, B, (int64_t)iy * B.nx + ix);
 }
 
 // One wavefront per tile.  Workgroups are dealt round-robin to the 8 XCDs;
-// remap so that XCD x gets the x-th contiguous slice of tiles.
-template <typename R, bool kDebug, typename Idx>
-__global__ __launch_bounds__(256) void march_uniform_kernel(const R* __restrict__ tv,
+// remap so that XCD x gets the x-th contiguous slice of tiles.  The FP32 loop
+// is held to 96 VGPRs (5 wavefronts per SIMD): the march waits on dependent
+// gathers, and the fifth wavefront hides more of that latency than the
+// compiler's unconstrained schedule (100 VGPRs, 4 wavefronts) gains.
+template <typename R, bool kDebug, typename Off>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
+void march_uniform_kernel(const R* __restrict__ tv,
                                                             TraceArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -219,14 +305,15 @@ __global__ __launch_bounds__(256) void march_uniform_kernel(const R* __restrict_
   const int64_t per = (nblk + 7) / 8;
   const int64_t xcd = blk % 8, slot = blk / 8;
   const int64_t vblk = xcd * per + slot;
-  const int64_t tile = vblk * (blockDim.x >> 6) + wave;
+  // the tile is the same for the 64 lanes: keep it (and the bundle) scalar
+  const int64_t tile = vblk * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
-  run_tile<R, kDebug, Idx>(tv, a, tile, lane);
+  run_tile<R, kDebug, Off>(tv, a, tile, lane);
 }
 
 // Persistent workgroups: every wavefront pulls tiles from a device counter
 // until the queue is drained (every wave reaches the exit test).
-template <typename R, bool kDebug, typename Idx>
+template <typename R, bool kDebug, typename Off>
 __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restrict__ tv,
                                                                 TraceArgs a) {
   const int lane = threadIdx.x & 63;
@@ -234,26 +321,74 @@ __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restr
     unsigned long long t = 0;
     if (lane == 0) t = atomicAdd(a.queue, 1ull);
     t = __shfl(t, 0, 64);
-    if ((int64_t)t >= a.n_tiles) break;
-    run_tile<R, kDebug, Idx>(tv, a, (int64_t)t, lane);
+    // the tile is the same for the 64 lanes: keep it (and the bundle) scalar
+    const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
+    if (tile >= a.n_tiles) break;
+    run_tile<R, kDebug, Off>(tv, a, tile, lane);
   }
 }
 
 __global__ void queue_reset_kernel(unsigned long long* q) { *q = 0ull; }
 
-template <typename R, bool kDebug, typename Idx>
+// Lattice bounds of the rays' end points (the walk between them stays in the
+// box they span).  One wavefront per tile, reduced across the wavefront
+// before one atomic per bound.
+__global__ __launch_bounds__(256) void ray_bounds_kernel(TraceArgs a, int* out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (tile >= a.n_tiles) return;
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+  const int b = find_bundle(a.bundles, a.n_bundles, tile);
+  const DevBundle& B = a.bundles[b];
+  const int64_t local = tile - B.tile_begin;
+  const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
+  const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
+  if (ix < B.nx && iy < B.ny) {
+    const int64_t ray = (int64_t)iy * B.nx + ix;
+    const double d[3] = {B.dir[3 * ray + 0], B.dir[3 * ray + 1], B.dir[3 * ray + 2]};
+    const double nrm2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (fabs(nrm2 - 1.0) <= 1e-9) {   // other rays are not traced
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int p0 = (int)floor(fma(B.chi_hi, d[k], a.o[k]));
+        const int p1 = (int)floor(fma(B.chi_lo, d[k], a.o[k]));
+        lo[k] = min(p0, p1);
+        hi[k] = max(p0, p1);
+      }
+    }
+  }
+#pragma unroll
+  for (int sh = 32; sh > 0; sh >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = min(lo[k], __shfl_xor(lo[k], sh, 64));
+      hi[k] = max(hi[k], __shfl_xor(hi[k], sh, 64));
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (lo[k] != INT_MAX) atomicMin(out + k, lo[k]);
+      if (hi[k] != INT_MIN) atomicMax(out + 3 + k, hi[k]);
+    }
+  }
+}
+
+template <typename R, bool kDebug, typename Off>
 hipError_t launch3(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
                    hipStream_t s) {
   const int wpb = block / 64;
   if (persistent) {
     const int blocks = (grid_waves + wpb - 1) / wpb;
-    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Idx>), dim3(blocks), dim3(block), 0, s,
+    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Off>), dim3(blocks), dim3(block), 0, s,
                        (const R*)tv, a);
   } else {
     int64_t blocks = (a.n_tiles + wpb - 1) / wpb;
     if (blocks == 0) return hipSuccess;
     blocks = (blocks + 7) / 8 * 8;   // the XCD remap is a bijection on multiples of 8
-    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Idx>), dim3((unsigned)blocks), dim3(block),
+    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Off>), dim3((unsigned)blocks), dim3(block),
                        0, s, (const R*)tv, a);
   }
   return hipGetLastError();
@@ -263,7 +398,8 @@ template <typename R>
 hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
                   hipStream_t s) {
   const bool dbg = a.hash || a.log || a.count;
-  const bool small = (int64_t)a.n * a.n * a.n < (1ll << 32);
+  // 32-bit byte offsets when the whole tensor is below 4 GiB
+  const bool small = (int64_t)a.n * a.n * a.n * (int64_t)(6 * sizeof(R)) < (1ll << 32);
   if (dbg)
     return small ? launch3<R, true, uint32_t>(tv, a, persistent, block, grid_waves, s)
                  : launch3<R, true, uint64_t>(tv, a, persistent, block, grid_waves, s);
@@ -277,6 +413,13 @@ hipError_t launch_march_uniform(int precision, const void* tv, const TraceArgs& 
                                 int block, int grid_waves, hipStream_t s) {
   if (precision == RR_PREC_FP32_KAHAN) return launch<float>(tv, a, persistent, block, grid_waves, s);
   return launch<double>(tv, a, persistent, block, grid_waves, s);
+}
+
+hipError_t launch_ray_bounds(const TraceArgs& a, int* out, hipStream_t s) {
+  const int64_t blocks = (a.n_tiles + 3) / 4;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(ray_bounds_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_queue_reset(unsigned long long* q, hipStream_t s) {

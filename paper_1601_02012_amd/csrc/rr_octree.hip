@@ -290,85 +290,129 @@ __global__ __launch_bounds__(256) void corner_kernel(Tree T, const Acc* __restri
 }
 
 // ------------------------------------------------------------------- march --
-__device__ __forceinline__ int slab_child(double o, double d, double r, int m, int l, double chi) {
+__device__ __forceinline__ int slab_child(double o, double r, int m, int l, double chi) {
   const double hl1 = ldexp(1.0, -(l + 1));
   const int mid = 2 * m + 1;
-  if (d == 0.0) return (o / hl1) >= (double)mid;
+  if (r == 0.0) return ldexp(o, l + 1) >= (double)mid;
   const double tm = tplane((double)mid * hl1, o, r);
-  return d > 0.0 ? (chi > tm) : (chi <= tm);
+  return r > 0.0 ? (chi > tm) : (chi <= tm);
 }
 
+// Project corners [c0, c0 + nc) of the leaf's corner block (8 corners x 6
+// components, 24 R each) on P.
+template <typename R, int c0, int nc>
+__device__ __forceinline__ void project_corners(const R* __restrict__ p, const R* P, R* q) {
+  R t[6 * nc];
+  if constexpr (sizeof(R) == 4) {
+    const float4* p4 = reinterpret_cast<const float4*>(p + 6 * c0);
+#pragma unroll
+    for (int i = 0; i < 6 * nc / 4; ++i) {
+      const float4 x = p4[i];
+      t[4 * i] = x.x; t[4 * i + 1] = x.y; t[4 * i + 2] = x.z; t[4 * i + 3] = x.w;
+    }
+  } else {
+    const double2* p2 = reinterpret_cast<const double2*>(p + 6 * c0);
+#pragma unroll
+    for (int i = 0; i < 3 * nc; ++i) {
+      const double2 x = p2[i];
+      t[2 * i] = x.x; t[2 * i + 1] = x.y;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < nc; ++v) {
+    R acc = P[0] * t[6 * v];
+#pragma unroll
+    for (int c = 1; c < 6; ++c) acc = fma(P[c], t[6 * v + c], acc);
+    q[c0 + v] = acc;
+  }
+}
+
+// The whole block in one go (all loads in flight): the per-crossing load.
 template <typename R>
 __device__ __forceinline__ void load_block(const R* __restrict__ cv, int64_t cell, const R* P,
-                                           R* q);
-template <>
-__device__ __forceinline__ void load_block<float>(const float* __restrict__ cv, int64_t cell,
-                                                  const float* P, float* q) {
-  const float4* p = reinterpret_cast<const float4*>(cv + 48 * cell);
-  float t[48];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) {
-    const float4 x = p[i];
-    t[4 * i] = x.x; t[4 * i + 1] = x.y; t[4 * i + 2] = x.z; t[4 * i + 3] = x.w;
-  }
-#pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    float acc = P[0] * t[6 * v];
-#pragma unroll
-    for (int c = 1; c < 6; ++c) acc = fmaf(P[c], t[6 * v + c], acc);
-    q[v] = acc;
-  }
-}
-template <>
-__device__ __forceinline__ void load_block<double>(const double* __restrict__ cv, int64_t cell,
-                                                   const double* P, double* q) {
-  const double2* p = reinterpret_cast<const double2*>(cv + 48 * cell);
-#pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    const double2 a = p[3 * v], b = p[3 * v + 1], c = p[3 * v + 2];
-    double acc = P[0] * a.x;
-    acc = fma(P[1], a.y, acc);
-    acc = fma(P[2], b.x, acc);
-    acc = fma(P[3], b.y, acc);
-    acc = fma(P[4], c.x, acc);
-    acc = fma(P[5], c.y, acc);
-    q[v] = acc;
-  }
+                                           R* q) {
+  project_corners<R, 0, 8>(cv + 48 * cell, P, q);
 }
 
+// The block in two halves, the second issued after the first is projected:
+// for the start of a ray, where the ray's set-up state is live as well.
+template <typename R>
+__device__ __forceinline__ void load_block_halves(const R* __restrict__ cv, int64_t cell,
+                                                  const R* P, R* q) {
+  const R* p = cv + 48 * cell;
+  project_corners<R, 0, 4>(p, P, q);
+  asm volatile("" : "+v"(p) : "v"(q[3]));
+  project_corners<R, 4, 4>(p, P, q);
+}
+
+// Cell at level l and coordinates I below base cell `b`; if the tree stops
+// above l, the covering leaf.  Returns the level of the cell found.
+__device__ __forceinline__ int descend_from(const Tree& T, int64_t b, int l, const int* I,
+                                            int64_t& cell) {
+  int64_t c = b;
+  for (int lev = 1; lev <= l; ++lev) {
+    const int k = T.child[c];
+    if (k < 0) {
+      cell = c;
+      return lev - 1;
+    }
+    const int s = l - lev;
+    const int ch = ((I[0] >> s) & 1) | (((I[1] >> s) & 1) << 1) | (((I[2] >> s) & 1) << 2);
+    c = T.nb + 8 * (int64_t)k + ch;
+  }
+  cell = c;
+  return l;
+}
+
+// One ray through the octree.  Per axis the lane keeps, in FP64, the
+// crossing parameter of the current leaf's exit plane, and the level-l
+// coordinates m; the leaf's local coordinate is u = A + S (chi - t_exit)
+// with S = n_a 2^l and A = 0 (n_a > 0, leaving through the lower face) or 1
+// (leaving through the upper face), so it is exact on the exit face.  The
+// wrapped base cell is tracked incrementally (no division per crossing).
+// The next leaf's corner block is loaded together with its child link: a
+// crossing that stays on level 0 or inside the parent oct needs no walk from
+// the base cell, and a refined target (the load is then discarded) or a
+// coarser one is walked.
 template <typename R, bool kDebug>
 __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceArgs& a,
                           const DevBundle& B, int64_t ray) {
   const int64_t out = B.ray_offset + ray;
-  const double d[3] = {B.dir[3 * ray + 0], B.dir[3 * ray + 1], B.dir[3 * ray + 2]};
-  const double nrm2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-  if (!(fabs(nrm2 - 1.0) <= 1e-9)) {
-    if (a.status) a.status[out] = RR_RAY_BAD_DIRECTION;
-    return;
-  }
-  double Pd[6];
-  projection(a.quantity, d[0], d[1], d[2], Pd);
-  R P[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) P[c] = (R)Pd[c];
-  double r[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) r[k] = (d[k] != 0.0) ? 1.0 / d[k] : 0.0;
-
+  const int n = T.n;
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
-  int m[3];
+  R P[6];
+  double r[3];
+  int m[3], wb[3];
+  {
+    const double d[3] = {B.dir[3 * ray + 0], B.dir[3 * ray + 1], B.dir[3 * ray + 2]};
+    const double nrm2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(fabs(nrm2 - 1.0) <= 1e-9)) {
+      if (a.status) a.status[out] = RR_RAY_BAD_DIRECTION;
+      return;
+    }
+    double Pd[6];
+    projection(a.quantity, d[0], d[1], d[2], Pd);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) m[k] = start_slab(a.o[k], d[k], r[k], chiA, 1.0);
+    for (int c = 0; c < 6; ++c) P[c] = (R)Pd[c];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      r[k] = (d[k] != 0.0) ? 1.0 / d[k] : 0.0;
+      m[k] = start_slab(a.o[k], d[k], r[k], chiA, 1.0);
+      const int q = m[k] % n;
+      wb[k] = q < 0 ? q + n : q;
+    }
+  }
+  int64_t blin = ((int64_t)wb[2] * n + wb[1]) * n + wb[0];
   int l = 0;
-  int64_t cell = base_of(T, 0, m);
+  int64_t cell = blin;
   {
     int k;
     while ((k = T.child[cell]) >= 0) {
       int ch = 0;
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        const int bit = slab_child(a.o[ax], d[ax], r[ax], m[ax], l, chiA);
+        const int bit = slab_child(a.o[ax], r[ax], m[ax], l, chiA);
         m[ax] = 2 * m[ax] + bit;
         ch |= bit << ax;
       }
@@ -376,6 +420,30 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       ++l;
     }
   }
+  double te[3];
+  R S[3], A[3];
+  // exit parameters and local-coordinate maps of every axis at level l
+  // (S = n_a 2^l is carried from level to level by exact power-of-two scaling)
+  auto set_level = [&](int dl) {
+    const double hl = ldexp(1.0, -l);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      S[k] = ldexp(S[k], dl);
+      if (r[k] != 0.0) {
+        te[k] = tplane((double)(r[k] > 0.0 ? m[k] : m[k] + 1) * hl, a.o[k], r[k]);
+        A[k] = r[k] > 0.0 ? (R)0 : (R)1;
+      } else {
+        // never crossed: slope 0 and a finite exit parameter below any chi
+        te[k] = -1e30;
+        A[k] = (R)ldexp(a.o[k] - (double)m[k] * hl, l);
+      }
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S[k] = (R)B.dir[3 * ray + k];
+  set_level(l);
+  R q[8];
+  load_block_halves<R>(cv, cell, P, q);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
@@ -397,12 +465,6 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       st = RR_RAY_MAX_STEPS;
       break;
     }
-    const double hl = ldexp(1.0, -l), inv_hl = ldexp(1.0, l);
-    double te[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      te[k] = d[k] != 0.0 ? tplane((double)(d[k] > 0.0 ? m[k] : m[k] + 1) * hl, a.o[k], r[k])
-                          : -__builtin_inf();
     double chiB = lo;
     chiB = te[0] > chiB ? te[0] : chiB;
     chiB = te[1] > chiB ? te[1] : chiB;
@@ -411,15 +473,11 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
 #pragma unroll
     for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
 
-    R q[8];
-    load_block<R>(cv, cell, P, q);
     R uA[3], uB[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double base = a.o[k] - (double)m[k] * hl;
-      uA[k] = (R)(fma(chiA, d[k], base) * inv_hl);
-      const R face = d[k] > 0.0 ? (R)0 : (R)1;
-      uB[k] = stepped[k] ? face : (R)(fma(chiB, d[k], base) * inv_hl);
+      uA[k] = fma(S[k], (R)(chiA - te[k]), A[k]);
+      uB[k] = fma(S[k], (R)(chiB - te[k]), A[k]);
     }
     const R L = (R)(chiA - chiB);
     const R ic = cell_integral<R>(q, uA, uB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
@@ -439,31 +497,71 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     }
     ++count;
     if (chiB == lo) break;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      if (stepped[k]) m[k] += d[k] > 0.0 ? -1 : 1;
     chiA = chiB;
-    // the leaf just past the crossed face(s)
-    int64_t nc;
-    const int lev = descend(T, l, m, nc);
-    if (lev < l) {
+
+    // step the crossed axes on level l; track the base cell
+    const int ch_old = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
+    bool sib = l > 0;
+    bool moved = false;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) m[k] >>= (l - lev);
-      l = lev;
-    } else {
-      int k;
-      while ((k = T.child[nc]) >= 0) {
-        int ch = 0;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          const int bit = stepped[ax] ? (d[ax] > 0.0 ? 1 : 0)
-                                      : slab_child(a.o[ax], d[ax], r[ax], m[ax], l, chiA);
-          m[ax] = 2 * m[ax] + bit;
-          ch |= bit << ax;
+    for (int k = 0; k < 3; ++k) {
+      if (stepped[k]) {
+        const int mo = m[k];
+        const int s = r[k] > 0.0 ? -1 : 1;
+        m[k] = mo + s;
+        sib = sib && ((m[k] >> 1) == (mo >> 1));
+        if ((m[k] >> l) != (mo >> l)) {
+          const int w = wb[k] + s;
+          wb[k] = w < 0 ? n - 1 : (w == n ? 0 : w);
+          moved = true;
         }
-        nc = T.nb + 8 * (int64_t)k + ch;
-        ++l;
       }
+    }
+    if (moved) blin = ((int64_t)wb[2] * n + wb[1]) * n + wb[0];
+    // the level-l cell past the face: a base cell, a sibling, or a walk
+    int64_t nc;
+    int lev = l;
+    if (l == 0) {
+      nc = blin;
+    } else if (sib) {
+      const int ch = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
+      nc = cell + (ch - ch_old);
+    } else {
+      lev = descend_from(T, blin, l, m, nc);
+    }
+    // load the target's corner block together with its child link; a refined
+    // target (rare) drops the block and descends to the child next to the
+    // crossed face(s), slab rule on the other axes
+    const int l_in = l;
+    for (;;) {
+      const int kc = T.child[nc];
+      load_block<R>(cv, nc, P, q);
+      if (kc < 0) break;
+      int ch = 0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const int bit = stepped[ax] ? (r[ax] > 0.0 ? 1 : 0)
+                                    : slab_child(a.o[ax], r[ax], m[ax], l, chiA);
+        m[ax] = 2 * m[ax] + bit;
+        ch |= bit << ax;
+      }
+      nc = T.nb + 8 * (int64_t)kc + ch;
+      ++l;
+    }
+    if (lev < l_in) {
+      // coarser neighbour
+#pragma unroll
+      for (int k = 0; k < 3; ++k) m[k] >>= (l_in - lev);
+      l = lev;
+    }
+    if (l != l_in) {
+      set_level(l - l_in);
+    } else {
+      const double hl = ldexp(1.0, -l);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (stepped[k])
+          te[k] = tplane((double)(r[k] > 0.0 ? m[k] : m[k] + 1) * hl, a.o[k], r[k]);
     }
     cell = nc;
   }
@@ -498,7 +596,9 @@ __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __re
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nblk = gridDim.x, blk = blockIdx.x;
   const int64_t per = (nblk + 7) / 8;
-  const int64_t tile = ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + wave;
+  // the tile is the same for the 64 lanes: keep it (and the bundle) scalar
+  const int64_t tile =
+      ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
   oct_tile<R, kDebug>(T, cv, a, tile, lane);
 }
@@ -511,8 +611,10 @@ __global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* 
     unsigned long long t = 0;
     if (lane == 0) t = atomicAdd(a.queue, 1ull);
     t = __shfl(t, 0, 64);
-    if ((int64_t)t >= a.n_tiles) break;
-    oct_tile<R, kDebug>(T, cv, a, (int64_t)t, lane);
+    const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
+    if (tile >= a.n_tiles) break;
+    oct_tile<R, kDebug>(T, cv, a, tile, lane);
   }
 }
 

@@ -11,6 +11,9 @@
 // Differences are always taken first on the raw potential (exact for
 // neighbours within a factor two, Sterbenz), sums afterwards.
 //
+// The vertices built are a periodic box [o, o + size) of the lattice (the
+// whole grid, or the part a set of rays can reach).
+//
 // Layout of the work: a workgroup owns a 64 x 4 column of vertices in x-y and
 // marches along z.  Each step stages one potential plane (plus a two-cell
 // halo) in LDS; every thread reads its 4 x 4 patch of that plane once and
@@ -48,20 +51,30 @@ __device__ inline void store_vertex<double>(double* dst, const double* r) {
   d2[2] = make_double2(r[4], r[5]);
 }
 
+struct VertexBox {
+  int ox, oy, oz;   // origin, wrapped into [0, n)
+  int sx, sy, sz;   // extent, at most n
+  int ntx, nty;     // workgroup tiles in x and y
+};
+
 template <typename In, typename Acc>
 __global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __restrict__ phi,
                                                                     Acc* __restrict__ tv, int n,
-                                                                    int open, int ntx, int nty) {
+                                                                    int open, VertexBox V) {
   constexpr int RW = VertexRecord<Acc>::kWords;
   __shared__ Acc plane[2][PY * PX];
 
   const int b = blockIdx.x;
-  const int bx = b % ntx;
-  const int by = (b / ntx) % nty;
-  const int bz = b / (ntx * nty);
-  const int i0 = bx * TX, j0 = by * TY, k0 = bz * KZ;
+  const int bx = b % V.ntx;
+  const int by = (b / V.ntx) % V.nty;
+  const int bz = b / (V.ntx * V.nty);
+  // box-local origin of this workgroup's column; lattice indices wrap
+  const int li0 = bx * TX, lj0 = by * TY, lk0 = bz * KZ;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int i = i0 + tx, j = j0 + ty;
+  const bool mine = li0 + tx < V.sx && lj0 + ty < V.sy;
+  int i = V.ox + li0 + tx, j = V.oy + lj0 + ty;
+  i = i >= n ? i - n : i;
+  j = j >= n ? j - n : j;
   const int64_t nn = (int64_t)n * n;
 
   // per-plane partial stencils, history over planes (index 0 = oldest)
@@ -79,16 +92,19 @@ __global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __
     const int e = threadIdx.x + 256 * u;
     sact[u] = e < PX * PY;
     const int lx = e % PX, ly = e / PX;
-    int gx = i0 - 2 + lx, gy = j0 - 2 + ly;
+    // unwrapped lattice coordinates (the open boundary pads outside [0, n))
+    const int gx = V.ox + li0 - 2 + lx, gy = V.oy + lj0 - 2 + ly;
     sin_[u] = gx >= 0 && gy >= 0 && gx < n && gy < n;
-    if (gx < 0) gx += n; else if (gx >= n) gx -= n;
-    if (gy < 0) gy += n; else if (gy >= n) gy -= n;
-    soff[u] = gy * n + gx;
+    int wx = gx % n, wy = gy % n;
+    wx = wx < 0 ? wx + n : wx;
+    wy = wy < 0 ? wy + n : wy;
+    soff[u] = wy * n + wx;
   }
 
-  const int k_end = min(k0 + KZ, n);
+  const int k0 = V.oz + lk0;                       // unwrapped
+  const int k_end = k0 + min(KZ, V.sz - lk0);
   int slot = 0;
-  int gz = k0 - 2;
+  int gz = (k0 - 2) % n;
   if (gz < 0) gz += n;
   for (int p = k0 - 2; p <= k_end; ++p, slot ^= 1) {
     // stage plane p (x fastest, wrapped or zero-padded)
@@ -137,9 +153,9 @@ __global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __
     DX[3][0] = dx[1]; DX[3][1] = dx[2];
     DY[3][0] = dy1; DY[3][1] = dy2;
 
-    if (p >= k0 + 1 && i < n && j < n) {
+    if (p >= k0 + 1 && mine) {
       // vertex k = p - 1: Z/DX/DY[0..3] are planes k-2..k+1; XX/YY/XY[0..1] are k-1, k
-      const int k = p - 1;
+      const int k = p - 1 >= n ? p - 1 - n : p - 1;
       Acc rec[6];
       rec[0] = (XX[0] + XX[1]) * (Acc)0.125;
       rec[1] = (YY[0] + YY[1]) * (Acc)0.125;
@@ -170,24 +186,39 @@ __global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __
 }
 
 template <typename In, typename Acc>
-hipError_t launch_vt(int n, int open, const void* phi, void* tv, hipStream_t s) {
-  const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY, ntz = (n + KZ - 1) / KZ;
-  const int64_t blocks = (int64_t)ntx * nty * ntz;
+hipError_t launch_vt(int n, int open, const int* lo, const int* size, const void* phi, void* tv,
+                     hipStream_t s) {
+  VertexBox V;
+  int o[3];
+  for (int a = 0; a < 3; ++a) {
+    o[a] = lo[a] % n;
+    if (o[a] < 0) o[a] += n;
+  }
+  V.ox = o[0]; V.oy = o[1]; V.oz = o[2];
+  V.sx = size[0]; V.sy = size[1]; V.sz = size[2];
+  V.ntx = (V.sx + TX - 1) / TX;
+  V.nty = (V.sy + TY - 1) / TY;
+  const int ntz = (V.sz + KZ - 1) / KZ;
+  const int64_t blocks = (int64_t)V.ntx * V.nty * ntz;
+  if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((vertex_tensor_uniform_kernel<In, Acc>), dim3((unsigned)blocks), dim3(256),
-                     0, s, (const In*)phi, (Acc*)tv, n, open, ntx, nty);
+                     0, s, (const In*)phi, (Acc*)tv, n, open, V);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int open,
-                                        const void* phi, void* tv, hipStream_t s) {
+// Vertices of the periodic box [lo, lo + size) (size[a] <= n; the host
+// layer validates).
+hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int open, const int* lo,
+                                        const int* size, const void* phi, void* tv,
+                                        hipStream_t s) {
   if (precision == RR_PREC_FP32_KAHAN) {
-    if (dtype == RR_F32) return launch_vt<float, float>(n, open, phi, tv, s);
-    return launch_vt<double, float>(n, open, phi, tv, s);
+    if (dtype == RR_F32) return launch_vt<float, float>(n, open, lo, size, phi, tv, s);
+    return launch_vt<double, float>(n, open, lo, size, phi, tv, s);
   }
-  if (dtype == RR_F32) return launch_vt<float, double>(n, open, phi, tv, s);
-  return launch_vt<double, double>(n, open, phi, tv, s);
+  if (dtype == RR_F32) return launch_vt<float, double>(n, open, lo, size, phi, tv, s);
+  return launch_vt<double, double>(n, open, lo, size, phi, tv, s);
 }
 
 }  // namespace rr

@@ -71,4 +71,8 @@ def test_host_validation_without_gpu(abi):
     assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -5      # malformed octree
     assert lib.rr_trace_rays(None, None, None, None, 0, None, None, None, None) == -1
     assert lib.rr_graph_launch(None, None) == -1
+    lo = (C.c_int32 * 3)(0, 0, 0)
+    assert lib.rr_build_tidal_tensor_box(None, None, lo, lo, None) == -1
+    assert "NULL" in abi.last_error()
+    assert lib.rr_rays_vertex_box(None, None, None, None, 0, lo, lo, None) == -1
     assert lib.rr_version() >= 10000
