@@ -80,8 +80,11 @@ typedef enum { RR_F32 = 0, RR_F64 = 1 } rr_dtype;
 /* Integrand: kappa (Eq. kappa), gamma_1 (Eq. gamma1), gamma_2 (Eq. gamma2 with
  * the mixed projection e_phi^T T e_theta). */
 typedef enum { RR_Q_KAPPA = 0, RR_Q_GAMMA1 = 1, RR_Q_GAMMA2 = 2 } rr_quantity;
-/* Per-cell integral: trilinear vertex reconstruction (Eq. Iclensing) or the
- * nearest-grid-point value of the cell centre (Eq. Iclensing_ngp). */
+/* Per-cell integral: trilinear vertex reconstruction (Eq. Iclensing, the
+ * tensor holds vertex records: rr_build_tidal_tensor) or the
+ * nearest-grid-point value of the cell centre times the integrated kernel
+ * (Eq. Iclensing_ngp, the tensor holds cell-centre records:
+ * rr_build_tidal_tensor_centres; octree tensors keep both). */
 typedef enum { RR_INTEGRAL_TRILINEAR = 0, RR_INTEGRAL_NGP = 1 } rr_integral;
 
 /* Per-ray status written to ray_status. */
@@ -133,6 +136,15 @@ rr_status rr_tensor_destroy(rr_tensor t);
  * at rr_tensor_create; values may change between calls (one call per N-body
  * step).  Asynchronous on s; no allocation. */
 rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s);
+
+/* Cell-centre tidal tensor (Eq. tidalexample, the cell's own level) for the
+ * nearest-grid-point integral (Eq. Iclensing_ngp): uniform tensors then hold
+ * one record per cell (cell i at record i, same 6-component layout) instead
+ * of vertex records, and trace with RR_INTEGRAL_NGP; tracing them with the
+ * trilinear integral returns RR_ERR_INVALID_ARG, and vice versa.  Open grids
+ * leave the outer cell layer NaN.  Octree tensors always hold both (this call
+ * is rr_build_tidal_tensor).  Asynchronous on s; no allocation. */
+rr_status rr_build_tidal_tensor_centres(rr_tensor t, const rr_field_desc* f, rr_stream s);
 
 /* The same tensor, built only on the vertices of the periodic box
  * [lo, lo + size) (vertex lattice indices; lo may lie outside [0, n) and the

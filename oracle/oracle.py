@@ -73,8 +73,8 @@ def lib():
         L.rro_corner_tensor_octree.argtypes = [vp, vp, vp]
         L.rro_corner_tensor_octree_cells.argtypes = [vp, vp, i64, vp, vp]
         L.rro_vertex_weights.argtypes = [i32, i32, i32, vp, vp, vp]
-        L.rro_trace_octree.argtypes = [vp, dbl, vp, i64, vp, vp, vp, vp, dbl, vp, vp, i64, i32,
-                                       vp, vp, vp, vp, vp, i64]
+        L.rro_trace_octree.argtypes = [vp, dbl, vp, i64, vp, vp, vp, vp, dbl, i32, vp, vp, i32,
+                                       i64, i32, vp, vp, vp, vp, vp, i64]
         L.rro_trace_octree.restype = i32
         L.rro_cell_integral.argtypes = [vp, vp, dbl, vp, vp, dbl, dbl, dbl]
         L.rro_cell_integral.restype = dbl
@@ -238,12 +238,16 @@ def vertex_weights(dim, n_coarse, n_fv):
 
 
 def trace_octree(t: Octree, box, observer, dirs, chi_s, chi_hi, chi_lo, *, cv=None, tc=None,
-                 phi=None, kappa_scale=1.0, max_steps=1 << 40, threads=0,
-                 log_stride=0) -> TraceResult:
+                 phi=None, kappa_scale=1.0, quantity=Q_KAPPA, ngp=False, max_steps=1 << 40,
+                 threads=0, log_stride=0) -> TraceResult:
+    """Trace rays through the octree (FP64).  ``ngp`` integrates each leaf's
+    centre tensor (Eq. Iclensing_ngp) instead of its corner reconstruction."""
     dirs = _f64(dirs).reshape(-1, 3)
     nr = dirs.shape[0]
-    if cv is None and tc is None:
+    if (cv is None or ngp) and tc is None:
         tc = centre_tensor_octree(t, phi)
+    if ngp:
+        cv = None
     kappa = np.zeros(nr)
     hsh = np.zeros(nr, dtype=np.uint64)
     ncr = np.zeros(nr, dtype=np.int64)
@@ -253,7 +257,8 @@ def trace_octree(t: Octree, box, observer, dirs, chi_s, chi_hi, chi_lo, *, cv=No
     tc_ = _f64(tc) if tc is not None else None
     lib().rro_trace_octree(t.ref(), float(box), _p(_f64(observer)), nr, _p(dirs),
                            _p(_per_ray(chi_s, nr)), _p(_per_ray(chi_hi, nr)),
-                           _p(_per_ray(chi_lo, nr)), float(kappa_scale), _p(cv_), _p(tc_),
-                           int(max_steps), int(threads), _p(kappa), _p(hsh), _p(ncr), _p(st),
+                           _p(_per_ray(chi_lo, nr)), float(kappa_scale), int(quantity),
+                           _p(cv_), _p(tc_), int(bool(ngp)), int(max_steps), int(threads), _p(kappa), _p(hsh),
+                           _p(ncr), _p(st),
                            _p(log), int(log_stride))
     return TraceResult(kappa, hsh, ncr, st, log)

@@ -112,11 +112,14 @@ void rro_vertex_weights(int32_t dim, int32_t n_coarse, int32_t n_fine, const int
                         double* alpha_coarse, double* alpha_fine /* n_fine */);
 /* Trace through an octree.  cv: per-leaf corner tensors from
  * rro_corner_tensor_octree, or NULL to evaluate each visited leaf's corners
- * on the fly from the centre tensor tc. */
+ * on the fly from the centre tensor tc.  ngp != 0 integrates the leaf's own
+ * centre tensor tc with Eq. (Iclensing_ngp) instead.  quantity as for
+ * rro_trace_uniform. */
 int32_t rro_trace_octree(const rro_octree* t, double box, const double* observer,
                          int64_t n_rays, const double* dir, const double* chi_s,
                          const double* chi_hi, const double* chi_lo, double kappa_scale,
-                         const double* cv, const double* tc, int64_t max_steps,
+                         int32_t quantity, const double* cv, const double* tc, int32_t ngp,
+                         int64_t max_steps,
                          int32_t n_threads, double* kappa, uint64_t* hash, int64_t* ncross,
                          int32_t* status, rro_segment* log, int64_t log_stride);
 

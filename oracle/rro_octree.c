@@ -330,7 +330,8 @@ static int slab_child(const rro_ray* ray, int a, int64_t m, int32_t l, double ch
 int32_t rro_trace_octree(const rro_octree* t, double box, const double* observer,
                          int64_t n_rays, const double* dir, const double* chi_s,
                          const double* chi_hi, const double* chi_lo, double kappa_scale,
-                         const double* cv, const double* tc, int64_t max_steps,
+                         int32_t quantity, const double* cv, const double* tc, int32_t ngp,
+                         int64_t max_steps,
                          int32_t n_threads, double* kappa, uint64_t* hash, int64_t* ncross,
                          int32_t* status, rro_segment* log, int64_t log_stride) {
   const double h0 = box / (double)t->n;
@@ -342,7 +343,7 @@ int32_t rro_trace_octree(const rro_octree* t, double box, const double* observer
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t r = 0; r < n_rays; ++r) {
     rro_ray ray;
-    rro_ray_init(&ray, dir + 3 * r, o, chi_s[r] / h0, RRO_Q_KAPPA);
+    rro_ray_init(&ray, dir + 3 * r, o, chi_s[r] / h0, quantity);
     const double lo = chi_lo[r] / h0;
     double chiA = chi_hi[r] / h0;
     int64_t m[3];
@@ -372,14 +373,19 @@ int32_t rro_trace_octree(const rro_octree* t, double box, const double* observer
       const double hl = ldexp(1.0, -l);
       int step[3];
       const double chiB = rro_exit(&ray, m, hl, chiA, lo, step);
-      double corner[8][6];
-      if (cv) {
-        memcpy(corner, cv + 48 * cur.cell, sizeof(corner));
+      if (ngp) {
+        /* Eq. (Iclensing_ngp): the leaf's own centre tensor */
+        sum += rro_integral_ngp(&ray, tc + 6 * cur.cell, chiA, chiB);
       } else {
-        leaf_corners(t, tc, cur.cell, corner);
+        double corner[8][6];
+        if (cv) {
+          memcpy(corner, cv + 48 * cur.cell, sizeof(corner));
+        } else {
+          leaf_corners(t, tc, cur.cell, corner);
+        }
+        const double p1[3] = {(double)m[0] * hl, (double)m[1] * hl, (double)m[2] * hl};
+        sum += rro_integral_trilinear(&ray, corner, p1, hl, chiA, chiB);
       }
-      const double p1[3] = {(double)m[0] * hl, (double)m[1] * hl, (double)m[2] * hl};
-      sum += rro_integral_trilinear(&ray, corner, p1, hl, chiA, chiB);
       if (log && count < log_stride) {
         rro_segment* s = log + r * log_stride + count;
         s->cell = cur.cell;

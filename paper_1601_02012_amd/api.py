@@ -99,6 +99,15 @@ class TidalTensor:
                 _lib.rr_build_tidal_tensor(self.handle, C.byref(d), _stream(stream)))
         return self
 
+    def build_centres(self, grid: Optional[Grid] = None, stream=None) -> "TidalTensor":
+        """rr_build_tidal_tensor_centres: cell-centre records for the NGP integral."""
+        g = grid if grid is not None else self.grid
+        self.grid = g
+        d = g.desc()
+        A.check("rr_build_tidal_tensor_centres",
+                _lib.rr_build_tidal_tensor_centres(self.handle, C.byref(d), _stream(stream)))
+        return self
+
     def build_box(self, lo, size, grid: Optional[Grid] = None, stream=None) -> "TidalTensor":
         """rr_build_tidal_tensor_box: rebuild only the vertices of the periodic box."""
         g = grid if grid is not None else self.grid
@@ -249,14 +258,14 @@ def _bundle_array(bundles: Sequence[RayBundle]):
 
 
 def _params(observer, precision, quantity="kappa", kappa_scale=1.0, persistent=-1,
-            max_crossings=0, hash=None, count=None, log=None, log_stride=0):
+            max_crossings=0, hash=None, count=None, log=None, log_stride=0, integral="trilinear"):
     tp = A.TraceParams()
     for k in range(3):
         tp.observer[k] = float(observer[k])
     tp.kappa_scale = float(kappa_scale)
     tp.precision = precision
     tp.quantity = QUANTITY[quantity] if isinstance(quantity, str) else int(quantity)
-    tp.integral = A.INTEGRAL_TRILINEAR
+    tp.integral = A.INTEGRAL_NGP if integral == "ngp" else A.INTEGRAL_TRILINEAR
     tp.persistent = int(persistent)
     tp.max_crossings = int(max_crossings)
     tp.crossing_hash = _ptr(hash)
@@ -287,8 +296,9 @@ def trace(plan: Plan, tensor: TidalTensor, bundles: Sequence[RayBundle], observe
           kappa: Optional[torch.Tensor] = None, kappa_comp: Optional[torch.Tensor] = None,
           status: Optional[torch.Tensor] = None, kappa_scale: float = 1.0, quantity="kappa",
           persistent: int = -1, max_crossings: int = 0, debug: bool = False,
-          log_stride: int = 0, stream=None) -> TraceOutput:
-    """rr_trace_rays: add each ray's integral to ``kappa`` (allocated if None)."""
+          log_stride: int = 0, integral: str = "trilinear", stream=None) -> TraceOutput:
+    """rr_trace_rays: add each ray's integral to ``kappa`` (allocated if None).
+    ``integral``: "trilinear" (vertex tensor) or "ngp" (cell-centre tensor)."""
     nr = total_rays(bundles)
     fp32 = tensor.precision == A.PREC_FP32_KAHAN
     dev = "cuda"
@@ -305,7 +315,7 @@ def trace(plan: Plan, tensor: TidalTensor, bundles: Sequence[RayBundle], observe
     if log_stride:
         log = torch.zeros((nr, log_stride, 3), dtype=torch.float64, device=dev)
     tp = _params(observer, tensor.precision, quantity, kappa_scale, persistent, max_crossings,
-                 hsh, cnt, log, log_stride)
+                 hsh, cnt, log, log_stride, integral)
     arr = _bundle_array(bundles)
     A.check("rr_trace_rays",
             _lib.rr_trace_rays(plan.handle, tensor.handle, C.byref(tp), arr, len(bundles),

@@ -53,6 +53,7 @@ struct rr_tensor_s {
   int64_t n_records = 0;
   int32_t record_bytes = 0;
   void* grad = nullptr;        // adjoint workspace (allocated on first use)
+  int32_t content = 0;         // uniform records: 0 unbuilt, 1 vertex tensors, 2 cell centres
   std::unique_ptr<rr::OctreeTensor> oct;
 };
 
@@ -198,6 +199,7 @@ rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s
                                             f->boundary == RR_BOUNDARY_OPEN, lo, size, f->values,
                                             t->data, (hipStream_t)s),
            "vertex tensor launch");
+    t->content = 1;
     return RR_OK;
   }
   if (f->n_cells != t->oct->n_cells || f->child_oct != t->oct->child_oct_dev)
@@ -225,10 +227,28 @@ rr_status rr_build_tidal_tensor_box(rr_tensor t, const rr_field_desc* f, const i
     if (f->boundary == RR_BOUNDARY_OPEN && (lo[a] < 0 || lo[a] + size[a] > n))
       return fail(RR_ERR_DOMAIN, "open grids take boxes inside [0, n)");
   }
+  if (t->content == 2)
+    return fail(RR_ERR_INVALID_ARG, "the tensor holds cell-centre records: rebuild it whole");
   RR_HIP(rr::launch_vertex_tensor_uniform(t->precision, f->dtype, n,
                                           f->boundary == RR_BOUNDARY_OPEN, lo, size, f->values,
                                           t->data, (hipStream_t)s),
          "vertex tensor launch");
+  t->content = 1;
+  return RR_OK;
+}
+
+rr_status rr_build_tidal_tensor_centres(rr_tensor t, const rr_field_desc* f, rr_stream s) {
+  if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  rr_status st = validate_field(f);
+  if (st != RR_OK) return st;
+  if (f->kind != t->kind || f->n_base != t->n || f->boundary != t->boundary)
+    return fail(RR_ERR_INVALID_ARG, "field does not match the grid the tensor was created for");
+  if (f->kind == RR_GRID_OCTREE) return rr_build_tidal_tensor(t, f, s);   // keeps both
+  RR_HIP(rr::launch_centre_tensor_uniform(t->precision, f->dtype, f->n_base,
+                                          f->boundary == RR_BOUNDARY_OPEN, f->values, t->data,
+                                          (hipStream_t)s),
+         "centre tensor launch");
+  t->content = 2;
   return RR_OK;
 }
 
@@ -276,10 +296,14 @@ rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle
                 tp->precision, t->precision);
   if (tp->quantity < RR_Q_KAPPA || tp->quantity > RR_Q_GAMMA2)
     return fail(RR_ERR_INVALID_ARG, "unknown quantity %d", tp->quantity);
-  if (tp->integral == RR_INTEGRAL_NGP)
-    return fail(RR_ERR_UNSUPPORTED, "the NGP per-cell integral is not implemented on the GPU");
-  if (tp->integral != RR_INTEGRAL_TRILINEAR)
+  if (tp->integral != RR_INTEGRAL_TRILINEAR && tp->integral != RR_INTEGRAL_NGP)
     return fail(RR_ERR_INVALID_ARG, "unknown integral %d", tp->integral);
+  if (t->kind == RR_GRID_UNIFORM && t->content != 0 &&
+      t->content != (tp->integral == RR_INTEGRAL_NGP ? 2 : 1))
+    return fail(RR_ERR_INVALID_ARG,
+                tp->integral == RR_INTEGRAL_NGP
+                    ? "the NGP integral reads cell-centre records (rr_build_tidal_tensor_centres)"
+                    : "the trilinear integral reads vertex records (rr_build_tidal_tensor)");
   if (!finite3(tp->observer)) return fail(RR_ERR_NONFINITE, "observer is not finite");
   const double h0 = t->box / (double)t->n;
   const double cell_cap = (double)(1 << 30);
@@ -404,8 +428,6 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp, const
   if (!kappa) return fail(RR_ERR_INVALID_ARG, "kappa is NULL");
   if (kappa_comp && t->precision != RR_PREC_FP32_KAHAN)
     return fail(RR_ERR_INVALID_ARG, "kappa_comp is only used by FP32_KAHAN");
-  if (tp->quantity != RR_Q_KAPPA && t->kind == RR_GRID_OCTREE)
-    return fail(RR_ERR_UNSUPPORTED, "shear on octrees is not implemented");
   const hipStream_t hs = (hipStream_t)s;
   int persistent = tp->persistent < 0 ? p->prefer_persistent : (tp->persistent ? 1 : 0);
   int block = 256, waves_per_cu = p->waves_per_cu;

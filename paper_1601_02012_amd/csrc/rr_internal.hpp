@@ -60,6 +60,9 @@ struct VertexRecord<double> {
 hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int open, const int* lo,
                                         const int* size, const void* phi, void* tv,
                                         hipStream_t s);
+// cell-centre tensor records (one per cell, same layout as the vertex records)
+hipError_t launch_centre_tensor_uniform(int precision, int dtype, int n, int open,
+                                        const void* phi, void* tc, hipStream_t s);
 // min / max over the rays of the floor of their lattice coordinates at both
 // ends of their chi windows: out[0..2] min, out[3..5] max (atomics; the
 // caller initialises out)

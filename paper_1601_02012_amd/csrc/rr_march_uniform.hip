@@ -84,7 +84,7 @@ __device__ __forceinline__ void load_corners(const R* __restrict__ tv, Off base,
 // wrapped index of the exit vertex layer; the cell's entry corner is one byte
 // offset into the vertex array (32 bit when the tensor is below 4 GiB), with
 // per-axis steps to the exit layer (modular arithmetic).
-template <typename R, bool kDebug, typename Off>
+template <typename R, bool kDebug, typename Off, bool kNgp>
 __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const DevBundle& B,
                           int64_t ray) {
   const int64_t out = B.ray_offset + ray;
@@ -145,7 +145,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   for (int k = 0; k < 3; ++k) fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
 
   R q[8];  // corner values, corner c = b0 + 2 b1 + 4 b2 in the ray frame
-  load_corners<R, Off>(tv, base, dX, P, q);
+  if constexpr (!kNgp) load_corners<R, Off>(tv, base, dX, P, q);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
@@ -193,7 +193,20 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
 #pragma unroll
     for (int k = 0; k < 3; ++k) fB[k] = (R)1 - absd[k] * (R)(chiB - te[k]);
     const R L = (R)(chiA - chiB);
-    const R ic = cell_integral<R>(q, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+    R ic;
+    if constexpr (kNgp) {
+      // Eq. (Iclensing_ngp): the cell-centre value times the integral of g over
+      // the piece, L (g(mid) - L^2 / (12 chi_s)) with g(chi) = chi (chi_s - chi) / chi_s
+      Off cellv = base;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cellv += r[k] > 0.0 ? dX[k] : (Off)0;
+      const R Qc = project<R, Off>(tv, cellv, P);
+      const double mid = chiB + 0.5 * (chiA - chiB);
+      const R gm = (R)mid * (R)(B.chi_s - mid) - L * L * (R)(1.0 / 12.0);
+      ic = Qc * (gm * L * inv_chis) * scale;
+    } else {
+      ic = cell_integral<R>(q, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+    }
     if constexpr (sizeof(R) == 4) {
       kahan_add(sum, comp, ic);
     } else {
@@ -238,7 +251,9 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
         }
       }
     }
-    if ((int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1) {
+    if constexpr (kNgp) {
+      // one record per cell: nothing carried from cell to cell
+    } else if ((int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1) {
       // one face crossed (axis k): keep its four values, load the new exit face,
       // whose corners F_j (j = i_a + 2 i_b over the two other axes a < b)
       const bool k0 = stepped[0], k1 = stepped[1];
@@ -278,7 +293,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   }
 }
 
-template <typename R, bool kDebug, typename Off>
+template <typename R, bool kDebug, typename Off, bool kNgp>
 __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -286,7 +301,7 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Off>(tv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Off, kNgp>(tv, a, B, (int64_t)iy * B.nx + ix);
 }
 
 // One wavefront per tile.  Workgroups are dealt round-robin to the 8 XCDs;
@@ -294,7 +309,7 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
 // is held to 96 VGPRs (5 wavefronts per SIMD): the march waits on dependent
 // gathers, and the fifth wavefront hides more of that latency than the
 // compiler's unconstrained schedule (100 VGPRs, 4 wavefronts) gains.
-template <typename R, bool kDebug, typename Off>
+template <typename R, bool kDebug, typename Off, bool kNgp>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
 void march_uniform_kernel(const R* __restrict__ tv,
                                                             TraceArgs a) {
@@ -308,12 +323,12 @@ void march_uniform_kernel(const R* __restrict__ tv,
   // the tile is the same for the 64 lanes: keep it (and the bundle) scalar
   const int64_t tile = vblk * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
-  run_tile<R, kDebug, Off>(tv, a, tile, lane);
+  run_tile<R, kDebug, Off, kNgp>(tv, a, tile, lane);
 }
 
 // Persistent workgroups: every wavefront pulls tiles from a device counter
 // until the queue is drained (every wave reaches the exit test).
-template <typename R, bool kDebug, typename Off>
+template <typename R, bool kDebug, typename Off, bool kNgp>
 __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restrict__ tv,
                                                                 TraceArgs a) {
   const int lane = threadIdx.x & 63;
@@ -325,7 +340,7 @@ __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restr
     const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
     if (tile >= a.n_tiles) break;
-    run_tile<R, kDebug, Off>(tv, a, tile, lane);
+    run_tile<R, kDebug, Off, kNgp>(tv, a, tile, lane);
   }
 }
 
@@ -376,19 +391,19 @@ __global__ __launch_bounds__(256) void ray_bounds_kernel(TraceArgs a, int* out) 
   }
 }
 
-template <typename R, bool kDebug, typename Off>
+template <typename R, bool kDebug, typename Off, bool kNgp>
 hipError_t launch3(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
                    hipStream_t s) {
   const int wpb = block / 64;
   if (persistent) {
     const int blocks = (grid_waves + wpb - 1) / wpb;
-    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Off>), dim3(blocks), dim3(block), 0, s,
+    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Off, kNgp>), dim3(blocks), dim3(block), 0, s,
                        (const R*)tv, a);
   } else {
     int64_t blocks = (a.n_tiles + wpb - 1) / wpb;
     if (blocks == 0) return hipSuccess;
     blocks = (blocks + 7) / 8 * 8;   // the XCD remap is a bijection on multiples of 8
-    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Off>), dim3((unsigned)blocks), dim3(block),
+    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Off, kNgp>), dim3((unsigned)blocks), dim3(block),
                        0, s, (const R*)tv, a);
   }
   return hipGetLastError();
@@ -400,11 +415,18 @@ hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block,
   const bool dbg = a.hash || a.log || a.count;
   // 32-bit byte offsets when the whole tensor is below 4 GiB
   const bool small = (int64_t)a.n * a.n * a.n * (int64_t)(6 * sizeof(R)) < (1ll << 32);
+  if (a.integral == RR_INTEGRAL_NGP) {
+    if (dbg)
+      return small ? launch3<R, true, uint32_t, true>(tv, a, persistent, block, grid_waves, s)
+                   : launch3<R, true, uint64_t, true>(tv, a, persistent, block, grid_waves, s);
+    return small ? launch3<R, false, uint32_t, true>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, false, uint64_t, true>(tv, a, persistent, block, grid_waves, s);
+  }
   if (dbg)
-    return small ? launch3<R, true, uint32_t>(tv, a, persistent, block, grid_waves, s)
-                 : launch3<R, true, uint64_t>(tv, a, persistent, block, grid_waves, s);
-  return small ? launch3<R, false, uint32_t>(tv, a, persistent, block, grid_waves, s)
-               : launch3<R, false, uint64_t>(tv, a, persistent, block, grid_waves, s);
+    return small ? launch3<R, true, uint32_t, false>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, true, uint64_t, false>(tv, a, persistent, block, grid_waves, s);
+  return small ? launch3<R, false, uint32_t, false>(tv, a, persistent, block, grid_waves, s)
+               : launch3<R, false, uint64_t, false>(tv, a, persistent, block, grid_waves, s);
 }
 
 }  // namespace

@@ -374,7 +374,7 @@ __device__ __forceinline__ int descend_from(const Tree& T, int64_t b, int l, con
 // crossing that stays on level 0 or inside the parent oct needs no walk from
 // the base cell, and a refined target (the load is then discarded) or a
 // coarser one is walked.
-template <typename R, bool kDebug>
+template <typename R, bool kDebug, bool kNgp>
 __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceArgs& a,
                           const DevBundle& B, int64_t ray) {
   const int64_t out = B.ray_offset + ray;
@@ -443,7 +443,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   for (int k = 0; k < 3; ++k) S[k] = (R)B.dir[3 * ray + k];
   set_level(l);
   R q[8];
-  load_block_halves<R>(cv, cell, P, q);
+  if constexpr (!kNgp) load_block_halves<R>(cv, cell, P, q);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
@@ -473,14 +473,27 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
 #pragma unroll
     for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
 
-    R uA[3], uB[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      uA[k] = fma(S[k], (R)(chiA - te[k]), A[k]);
-      uB[k] = fma(S[k], (R)(chiB - te[k]), A[k]);
-    }
     const R L = (R)(chiA - chiB);
-    const R ic = cell_integral<R>(q, uA, uB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+    R ic;
+    if constexpr (kNgp) {
+      // Eq. (Iclensing_ngp): the leaf's centre value times the integral of g,
+      // L (g(mid) - L^2 / (12 chi_s)) with g(chi) = chi (chi_s - chi) / chi_s
+      const R* tc = cv + 6 * cell;
+      R Qc = P[0] * tc[0];
+#pragma unroll
+      for (int c = 1; c < 6; ++c) Qc = fma(P[c], tc[c], Qc);
+      const double mid = chiB + 0.5 * (chiA - chiB);
+      const R gm = (R)mid * (R)(B.chi_s - mid) - L * L * (R)(1.0 / 12.0);
+      ic = Qc * (gm * L * inv_chis) * scale;
+    } else {
+      R uA[3], uB[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        uA[k] = fma(S[k], (R)(chiA - te[k]), A[k]);
+        uB[k] = fma(S[k], (R)(chiB - te[k]), A[k]);
+      }
+      ic = cell_integral<R>(q, uA, uB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+    }
     if constexpr (sizeof(R) == 4) {
       kahan_add(sum, comp, ic);
     } else {
@@ -535,7 +548,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     const int l_in = l;
     for (;;) {
       const int kc = T.child[nc];
-      load_block<R>(cv, nc, P, q);
+      if constexpr (!kNgp) load_block<R>(cv, nc, P, q);
       if (kc < 0) break;
       int ch = 0;
 #pragma unroll
@@ -579,7 +592,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   }
 }
 
-template <typename R, bool kDebug>
+template <typename R, bool kDebug, bool kNgp>
 __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -587,10 +600,10 @@ __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const Trace
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug>(T, cv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kNgp>(T, cv, a, B, (int64_t)iy * B.nx + ix);
 }
 
-template <typename R, bool kDebug>
+template <typename R, bool kDebug, bool kNgp>
 __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __restrict__ cv,
                                                            TraceArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -600,10 +613,10 @@ __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __re
   const int64_t tile =
       ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
-  oct_tile<R, kDebug>(T, cv, a, tile, lane);
+  oct_tile<R, kDebug, kNgp>(T, cv, a, tile, lane);
 }
 
-template <typename R, bool kDebug>
+template <typename R, bool kDebug, bool kNgp>
 __global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* __restrict__ cv,
                                                                TraceArgs a) {
   const int lane = threadIdx.x & 63;
@@ -614,22 +627,22 @@ __global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* 
     const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
     if (tile >= a.n_tiles) break;
-    oct_tile<R, kDebug>(T, cv, a, tile, lane);
+    oct_tile<R, kDebug, kNgp>(T, cv, a, tile, lane);
   }
 }
 
-template <typename R, bool kDebug>
+template <typename R, bool kDebug, bool kNgp>
 hipError_t launch_march(const Tree& T, const void* cv, const TraceArgs& a, int persistent,
                         int grid_waves, hipStream_t s) {
   if (persistent) {
     const int blocks = (grid_waves + 3) / 4;
-    hipLaunchKernelGGL((march_octree_persistent<R, kDebug>), dim3(blocks), dim3(256), 0, s, T,
+    hipLaunchKernelGGL((march_octree_persistent<R, kDebug, kNgp>), dim3(blocks), dim3(256), 0, s, T,
                        (const R*)cv, a);
   } else {
     int64_t blocks = (a.n_tiles + 3) / 4;
     if (blocks == 0) return hipSuccess;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL((march_octree_kernel<R, kDebug>), dim3((unsigned)blocks), dim3(256), 0, s,
+    hipLaunchKernelGGL((march_octree_kernel<R, kDebug, kNgp>), dim3((unsigned)blocks), dim3(256), 0, s,
                        T, (const R*)cv, a);
   }
   return hipGetLastError();
@@ -675,11 +688,18 @@ hipError_t OctreeTensor::march(const TraceArgs& a, int persistent, int grid_wave
   if (a.n_tiles == 0) return hipSuccess;
   Tree T{child_oct_dev, reinterpret_cast<const int4*>(oct_info), n, (int64_t)n * n * n};
   const bool dbg = a.hash || a.log || a.count;
+  if (a.integral == RR_INTEGRAL_NGP) {   // cell-centre records, 6 per cell
+    if (precision == RR_PREC_FP32_KAHAN)
+      return dbg ? launch_march<float, true, true>(T, centre, a, persistent, grid_waves, s)
+                 : launch_march<float, false, true>(T, centre, a, persistent, grid_waves, s);
+    return dbg ? launch_march<double, true, true>(T, centre, a, persistent, grid_waves, s)
+               : launch_march<double, false, true>(T, centre, a, persistent, grid_waves, s);
+  }
   if (precision == RR_PREC_FP32_KAHAN)
-    return dbg ? launch_march<float, true>(T, corners, a, persistent, grid_waves, s)
-               : launch_march<float, false>(T, corners, a, persistent, grid_waves, s);
-  return dbg ? launch_march<double, true>(T, corners, a, persistent, grid_waves, s)
-             : launch_march<double, false>(T, corners, a, persistent, grid_waves, s);
+    return dbg ? launch_march<float, true, false>(T, corners, a, persistent, grid_waves, s)
+               : launch_march<float, false, false>(T, corners, a, persistent, grid_waves, s);
+  return dbg ? launch_march<double, true, false>(T, corners, a, persistent, grid_waves, s)
+             : launch_march<double, false, false>(T, corners, a, persistent, grid_waves, s);
 }
 
 }  // namespace rr

@@ -14,41 +14,54 @@
 // The vertices built are a periodic box [o, o + size) of the lattice (the
 // whole grid, or the part a set of rays can reach).
 //
-// Layout of the work: a workgroup owns a 64 x 4 column of vertices in x-y and
-// marches along z.  Each step stages one potential plane (plus a two-cell
-// halo) in LDS; every thread reads its 4 x 4 patch of that plane once and
-// keeps the per-plane partial stencils of the last four planes in registers,
-// so each potential value is read from HBM about once and each vertex costs
-// 16 LDS reads and ~80 arithmetic operations.
+// Layout of the work: a workgroup owns a 64 x TY column of vertices in x-y
+// and marches KZ vertices along z.  Each step stages one potential plane
+// (plus a two-cell halo) in LDS; every thread reads its 4 x 4 patch of that
+// plane once and keeps the per-plane partial stencils of the last four planes
+// in registers, so each vertex costs 16 LDS reads and ~80 arithmetic
+// operations.  Whole-grid builds take 64 x 8 x 64 columns (the halo re-reads
+// 1.4 potential values per vertex) and write the records with non-temporal
+// stores (the 3 GiB tensor of a 512^3 grid does not fit any cache); small
+// boxes take 64 x 4 x 32 columns and ordinary stores, since the march reads
+// them right away.
 #include "rr_internal.hpp"
 
 namespace rr {
 namespace {
 
-constexpr int TX = 64, TY = 4;          // vertices per workgroup in x, y
-constexpr int PX = TX + 3, PY = TY + 3; // staged plane: halo 2 below, 1 above
-constexpr int KZ = 32;                  // vertices per workgroup along z
+constexpr int TX = 64;                  // vertices per workgroup in x
 
 __device__ inline int wrapi(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
 
-template <typename Out>
-__device__ inline void store_vertex(Out* dst, const Out* rec);
-template <>
-__device__ inline void store_vertex<float>(float* dst, const float* r) {
-  float2* d2 = reinterpret_cast<float2*>(dst);
-  d2[0] = make_float2(r[0], r[1]);
-  d2[1] = make_float2(r[2], r[3]);
-  d2[2] = make_float2(r[4], r[5]);
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <bool kNT>
+__device__ inline void store_vertex(float* dst, const float* r) {
+  f32x2* d = reinterpret_cast<f32x2*>(dst);
+  const f32x2 a = {r[0], r[1]}, b = {r[2], r[3]}, c = {r[4], r[5]};
+  if constexpr (kNT) {
+    __builtin_nontemporal_store(a, d);
+    __builtin_nontemporal_store(b, d + 1);
+    __builtin_nontemporal_store(c, d + 2);
+  } else {
+    d[0] = a; d[1] = b; d[2] = c;
+  }
 }
-template <>
-__device__ inline void store_vertex<double>(double* dst, const double* r) {
-  double2* d2 = reinterpret_cast<double2*>(dst);
-  d2[0] = make_double2(r[0], r[1]);
-  d2[1] = make_double2(r[2], r[3]);
-  d2[2] = make_double2(r[4], r[5]);
+template <bool kNT>
+__device__ inline void store_vertex(double* dst, const double* r) {
+  f64x2* d = reinterpret_cast<f64x2*>(dst);
+  const f64x2 a = {r[0], r[1]}, b = {r[2], r[3]}, c = {r[4], r[5]};
+  if constexpr (kNT) {
+    __builtin_nontemporal_store(a, d);
+    __builtin_nontemporal_store(b, d + 1);
+    __builtin_nontemporal_store(c, d + 2);
+  } else {
+    d[0] = a; d[1] = b; d[2] = c;
+  }
 }
 
 struct VertexBox {
@@ -57,11 +70,14 @@ struct VertexBox {
   int ntx, nty;     // workgroup tiles in x and y
 };
 
-template <typename In, typename Acc>
-__global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __restrict__ phi,
-                                                                    Acc* __restrict__ tv, int n,
-                                                                    int open, VertexBox V) {
+template <typename In, typename Acc, int TY, int KZ, bool kNT>
+__global__ __launch_bounds__(64 * TY) void vertex_tensor_uniform_kernel(const In* __restrict__ phi,
+                                                                        Acc* __restrict__ tv,
+                                                                        int n, int open,
+                                                                        VertexBox V) {
   constexpr int RW = VertexRecord<Acc>::kWords;
+  constexpr int NT = TX * TY;                 // threads
+  constexpr int PX = TX + 3, PY = TY + 3;     // staged plane: halo 2 below, 1 above
   __shared__ Acc plane[2][PY * PX];
 
   const int b = blockIdx.x;
@@ -84,12 +100,12 @@ __global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __
 
   // staging: each thread copies at most two elements of every plane; their
   // (wrapped) x-y offsets are fixed for the whole march
-  constexpr int kStage = (PX * PY + 255) / 256;
+  constexpr int kStage = (PX * PY + NT - 1) / NT;
   int soff[kStage];
   bool sin_[kStage], sact[kStage];
 #pragma unroll
   for (int u = 0; u < kStage; ++u) {
-    const int e = threadIdx.x + 256 * u;
+    const int e = threadIdx.x + NT * u;
     sact[u] = e < PX * PY;
     const int lx = e % PX, ly = e / PX;
     // unwrapped lattice coordinates (the open boundary pads outside [0, n))
@@ -119,7 +135,7 @@ __global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __
         v = (sin_[u] && zin) ? (Acc)src[soff[u]] : (Acc)0;
       else
         v = (Acc)src[soff[u]];
-      pl[threadIdx.x + 256 * u] = v;
+      pl[threadIdx.x + NT * u] = v;
     }
     if (++gz == n) gz = 0;
     __syncthreads();
@@ -177,12 +193,67 @@ __global__ __launch_bounds__(256) void vertex_tensor_uniform_kernel(const In* __
 #pragma unroll
         for (int c = 0; c < 6; ++c) rec[c] = nan;
       }
-      store_vertex<Acc>(tv + ((int64_t)k * nn + (int64_t)j * n + i) * RW, rec);
+      store_vertex<kNT>(tv + ((int64_t)k * nn + (int64_t)j * n + i) * RW, rec);
     }
     // XX/YY/XY hold planes (p-2, p-1) during step p; push plane p
     XX[0] = XX[1]; YY[0] = YY[1]; XY[0] = XY[1];
     XX[1] = sxx; YY[1] = syy; XY[1] = dxy;
   }
+}
+
+// Cell-centre tensor (Eq. tidalexample, cell size 1), one cell per thread,
+// for the nearest-grid-point integral (Eq. Iclensing_ngp).  Second
+// differences as differences of differences, mixed ones over the four
+// diagonal neighbours; open grids leave the outer cell layer NaN (no stencil).
+template <typename In, typename Acc>
+__global__ __launch_bounds__(256) void centre_tensor_uniform_kernel(const In* __restrict__ phi,
+                                                                    Acc* __restrict__ tc, int n,
+                                                                    int open) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= nn * n) return;
+  const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / nn);
+  Acc rec[6];
+  if (open && (i < 1 || j < 1 || k < 1 || i > n - 2 || j > n - 2 || k > n - 2)) {
+#pragma unroll
+    for (int u = 0; u < 6; ++u) rec[u] = (Acc)__builtin_nan("");
+  } else {
+    const int im = i == 0 ? n - 1 : i - 1, ip = i + 1 == n ? 0 : i + 1;
+    const int jm = j == 0 ? n - 1 : j - 1, jp = j + 1 == n ? 0 : j + 1;
+    const int km = k == 0 ? n - 1 : k - 1, kp = k + 1 == n ? 0 : k + 1;
+    auto P = [&](int x, int y, int z) -> Acc { return (Acc)phi[(int64_t)z * nn + (int64_t)y * n + x]; };
+    const Acc c0 = P(i, j, k);
+    rec[0] = (P(ip, j, k) - c0) - (c0 - P(im, j, k));
+    rec[1] = (P(i, jp, k) - c0) - (c0 - P(i, jm, k));
+    rec[2] = (P(i, j, kp) - c0) - (c0 - P(i, j, km));
+    rec[3] = ((P(ip, jp, k) - P(ip, jm, k)) - (P(im, jp, k) - P(im, jm, k))) * (Acc)0.25;
+    rec[4] = ((P(ip, j, kp) - P(ip, j, km)) - (P(im, j, kp) - P(im, j, km))) * (Acc)0.25;
+    rec[5] = ((P(i, jp, kp) - P(i, jp, km)) - (P(i, jm, kp) - P(i, jm, km))) * (Acc)0.25;
+  }
+  store_vertex<false>(tc + c * 6, rec);
+}
+
+template <typename In, typename Acc>
+hipError_t launch_ct(int n, int open, const void* phi, void* tc, hipStream_t s) {
+  const int64_t blocks = ((int64_t)n * n * n + 255) / 256;
+  hipLaunchKernelGGL((centre_tensor_uniform_kernel<In, Acc>), dim3((unsigned)blocks), dim3(256),
+                     0, s, (const In*)phi, (Acc*)tc, n, open);
+  return hipGetLastError();
+}
+
+template <typename In, typename Acc, int TY, int KZ, bool kNT>
+hipError_t launch_shape(const VertexBox& box, int n, int open, const void* phi, void* tv,
+                        hipStream_t s) {
+  VertexBox V = box;
+  V.ntx = (V.sx + TX - 1) / TX;
+  V.nty = (V.sy + TY - 1) / TY;
+  const int ntz = (V.sz + KZ - 1) / KZ;
+  const int64_t blocks = (int64_t)V.ntx * V.nty * ntz;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((vertex_tensor_uniform_kernel<In, Acc, TY, KZ, kNT>),
+                     dim3((unsigned)blocks), dim3(TX * TY), 0, s, (const In*)phi, (Acc*)tv, n,
+                     open, V);
+  return hipGetLastError();
 }
 
 template <typename In, typename Acc>
@@ -196,14 +267,11 @@ hipError_t launch_vt(int n, int open, const int* lo, const int* size, const void
   }
   V.ox = o[0]; V.oy = o[1]; V.oz = o[2];
   V.sx = size[0]; V.sy = size[1]; V.sz = size[2];
-  V.ntx = (V.sx + TX - 1) / TX;
-  V.nty = (V.sy + TY - 1) / TY;
-  const int ntz = (V.sz + KZ - 1) / KZ;
-  const int64_t blocks = (int64_t)V.ntx * V.nty * ntz;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((vertex_tensor_uniform_kernel<In, Acc>), dim3((unsigned)blocks), dim3(256),
-                     0, s, (const In*)phi, (Acc*)tv, n, open, V);
-  return hipGetLastError();
+  const int64_t nv = (int64_t)V.sx * V.sy * V.sz;
+  // boxes beyond 1/8 of the grid stream through HBM like the whole grid
+  if (8 * nv > (int64_t)n * n * n)
+    return launch_shape<In, Acc, 8, 64, true>(V, n, open, phi, tv, s);
+  return launch_shape<In, Acc, 4, 32, false>(V, n, open, phi, tv, s);
 }
 
 }  // namespace
@@ -219,6 +287,16 @@ hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int ope
   }
   if (dtype == RR_F32) return launch_vt<float, double>(n, open, lo, size, phi, tv, s);
   return launch_vt<double, double>(n, open, lo, size, phi, tv, s);
+}
+
+hipError_t launch_centre_tensor_uniform(int precision, int dtype, int n, int open,
+                                        const void* phi, void* tc, hipStream_t s) {
+  if (precision == RR_PREC_FP32_KAHAN) {
+    if (dtype == RR_F32) return launch_ct<float, float>(n, open, phi, tc, s);
+    return launch_ct<double, float>(n, open, phi, tc, s);
+  }
+  if (dtype == RR_F32) return launch_ct<float, double>(n, open, phi, tc, s);
+  return launch_ct<double, double>(n, open, phi, tc, s);
 }
 
 }  // namespace rr

@@ -221,3 +221,23 @@ def test_refinement_across_the_periodic_faces(api, oracle, plan, prec):
     else:
         ok, worst = kappa_tolerance_ok(k, r.kappa)
         assert ok, worst
+
+
+@pytest.mark.parametrize("quantity,q", [("gamma1", 1), ("gamma2", 2)])
+def test_octree_shear_matches_oracle(api, oracle, plan, tree_case, quantity, q):
+    import torch
+    t, box, phi = tree_case
+    g = _gpu_octree_grid(api, t, phi, box, np.float64)
+    tt = api.TidalTensor(g, "fp64").build()
+    fov = math.radians(40.0)
+    nx, ny = 17, 11
+    dirs = I.fov_directions((0.2, 0.1, 1.0), fov, fov * 0.6, nx, ny)
+    obs = (11.7, 12.2, 3.1)
+    chis, hi, lo = 60.0, 45.0, 0.2
+    b = api.RayBundle(torch.as_tensor(dirs).cuda(), nx, ny, chis, hi, lo)
+    out = api.trace(plan, tt, [b], obs, debug=True, quantity=quantity)
+    ref = oracle.trace_octree(_otree(oracle, t), box, obs, dirs, chis, hi, lo, phi=phi,
+                              quantity=q)
+    assert np.array_equal(hashes_u64(out.hash), ref.hash)
+    k = out.kappa.cpu().numpy()
+    np.testing.assert_allclose(k, ref.kappa, rtol=0, atol=1e-11 * np.abs(ref.kappa).max())

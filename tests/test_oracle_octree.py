@@ -153,6 +153,61 @@ def test_P2_quadratic_on_octree_refinement_invariant(oracle, seed):
     np.testing.assert_allclose(r.kappa, expect, rtol=1e-11)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_P2_quadratic_ngp_on_octree(oracle, seed):
+    """Eq. (Iclensing_ngp) on a multi-level octree: a quadratic potential has
+    the same exact centre tensor in every leaf, so the nearest-grid-point
+    kappa is the constant times the kernel integral, and the walk (crossing
+    hashes) is the one of the trilinear integral."""
+    rng = np.random.default_rng(300 + seed)
+    n, L = 16, 16.0
+    t = I.random_octree(n, 3, 0.25, rng, region=(3.0, 13.0))
+    ot = _otree(oracle, t)
+    M = rng.normal(size=(3, 3)); M = M + M.T
+    cen = t.centres(L)
+    phi = 0.5 * np.einsum("ci,ij,cj->c", cen, M, cen)
+    o = np.array([8.0, 8.0, 3.5])
+    fov = math.radians(20.0)
+    dirs = I.fov_directions((0.0, 0.0, 1.0), fov, fov, 7, 7)
+    chis, hi, lo = 12.0, 9.0, 0.0
+    r = oracle.trace_octree(ot, L, o, dirs, chis, hi, lo, phi=phi, ngp=True)
+    rt = oracle.trace_octree(ot, L, o, dirs, chis, hi, lo, phi=phi)
+    assert np.array_equal(r.hash, rt.hash)
+    qv = np.trace(M) - np.einsum("ri,ij,rj->r", dirs, M, dirs)
+    expect = qv * ((chis * (hi ** 2 - lo ** 2) / 2 - (hi ** 3 - lo ** 3) / 3) / chis)
+    # per-cell closed forms cancel: rounding is relative to the map's scale
+    np.testing.assert_allclose(r.kappa, expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+
+
+def test_P2_quadratic_shear_on_octree(oracle):
+    """Constant tensor on a multi-level octree: gamma1 and gamma2 are the
+    projections on e_theta, e_phi (Eqs. gamma1, gamma2, Eq. n1n2 read without
+    its 1/sin(theta)) times the kernel integral, whatever the refinement."""
+    rng = np.random.default_rng(320)
+    n, L = 16, 16.0
+    t = I.random_octree(n, 3, 0.25, rng, region=(3.0, 13.0))
+    ot = _otree(oracle, t)
+    M = rng.normal(size=(3, 3)); M = M + M.T
+    cen = t.centres(L)
+    phi = 0.5 * np.einsum("ci,ij,cj->c", cen, M, cen)
+    o = np.array([8.0, 8.0, 3.5])
+    fov = math.radians(20.0)
+    dirs = I.fov_directions((0.1, 0.0, 1.0), fov, fov, 7, 7)
+    chis, hi, lo = 12.0, 9.0, 0.0
+    gint = (chis * (hi ** 2 - lo ** 2) / 2 - (hi ** 3 - lo ** 3) / 3) / chis
+    th = np.arccos(dirs[:, 2])
+    ph = np.arctan2(dirs[:, 1], dirs[:, 0])
+    et = np.stack([np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), -np.sin(th)], 1)
+    ep = np.stack([-np.sin(ph), np.cos(ph), np.zeros_like(ph)], 1)
+    quad = lambda u, v: np.einsum("ri,ij,rj->r", u, M, v)
+    g1 = oracle.trace_octree(ot, L, o, dirs, chis, hi, lo, phi=phi, quantity=oracle.Q_GAMMA1)
+    g2 = oracle.trace_octree(ot, L, o, dirs, chis, hi, lo, phi=phi, quantity=oracle.Q_GAMMA2)
+    e1 = (quad(ep, ep) - quad(et, et)) * gint
+    e2 = 2 * quad(ep, et) * gint
+    np.testing.assert_allclose(g1.kappa, e1, rtol=0, atol=1e-11 * np.abs(e1).max())
+    np.testing.assert_allclose(g2.kappa, e2, rtol=0, atol=1e-11 * np.abs(e2).max())
+
+
 def test_P8_face_centre_hanging_vertex(oracle):
     """A vertex in the middle of a coarse face takes the mean of the face's
     four coarse corner values (Sec. III F, text after Eq. rhoV_1)."""
