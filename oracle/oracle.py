@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle_rro.so")
-SOURCES = ["rro_uniform.c", "rro_adjoint.c", "rro_octree.c"]
+SOURCES = ["rro_uniform.c", "rro_adjoint.c", "rro_octree.c", "rro_method_a.c"]
 
 RAY_OK, RAY_OUT_OF_DOMAIN, RAY_MAX_STEPS = 0, 1, 2
 Q_KAPPA, Q_GAMMA1, Q_GAMMA2 = 0, 1, 2
@@ -78,6 +78,12 @@ def lib():
         L.rro_trace_octree.restype = i32
         L.rro_cell_integral.argtypes = [vp, vp, dbl, vp, vp, dbl, dbl, dbl]
         L.rro_cell_integral.restype = dbl
+        L.rro_cell_integral_k.argtypes = [vp, vp, dbl, vp, vp, dbl, dbl, dbl]
+        L.rro_cell_integral_k.restype = dbl
+        L.rro_method_a_vertex_fields.argtypes = [i32, i32, dbl, vp, vp, vp]
+        L.rro_trace_uniform_method_a.argtypes = [i32, i32, dbl, vp, i64, vp, vp, vp, vp, dbl, dbl,
+                                                 vp, i64, i32, vp, vp, vp, vp]
+        L.rro_trace_uniform_method_a.restype = i32
         L.rro_projection.argtypes = [vp, vp, i32]
         L.rro_projection.restype = dbl
         _lib = L
@@ -154,6 +160,45 @@ def trace_uniform(n, box, observer, dirs, chi_s, chi_hi, chi_lo, *, tv=None, tc=
                             _p(tc_), int(max_steps), int(threads), _p(kappa), _p(hsh),
                             _p(ncr), _p(st), _p(log), int(log_stride))
     return TraceResult(kappa, hsh, ncr, st, log)
+
+
+def method_a_vertex_fields(phi, delta, open_boundary=False, h=1.0):
+    """Method A vertex fields (Eq. kappa2): per vertex (delta, dPhi/dx, dPhi/dy,
+    dPhi/dz), central differences and the eight-cell mean; returns (n^3, 4)."""
+    phi = _f64(phi)
+    delta = _f64(delta)
+    n = phi.shape[0]
+    fv = np.empty((n ** 3, 4))
+    lib().rro_method_a_vertex_fields(n, int(open_boundary), h, _p(phi), _p(delta), _p(fv))
+    return fv
+
+
+def trace_uniform_method_a(n, box, observer, dirs, chi_s, chi_hi, chi_lo, *, delta_coeff,
+                           fv=None, phi=None, delta=None, open_boundary=False, kappa_scale=1.0,
+                           max_steps=1 << 40, threads=0) -> TraceResult:
+    """Method A kappa (FP64): delta_coeff g delta + (n . grad Phi) dg/dchi and
+    the step's surface term; ``fv`` from method_a_vertex_fields, or ``phi`` and
+    ``delta`` to compute it here."""
+    dirs = _f64(dirs).reshape(-1, 3)
+    nr = dirs.shape[0]
+    if fv is None:
+        fv = method_a_vertex_fields(phi, delta, open_boundary)
+    kappa = np.zeros(nr)
+    hsh = np.zeros(nr, dtype=np.uint64)
+    ncr = np.zeros(nr, dtype=np.int64)
+    st = np.zeros(nr, dtype=np.int32)
+    lib().rro_trace_uniform_method_a(n, int(open_boundary), float(box), _p(_f64(observer)), nr,
+                                     _p(dirs), _p(_per_ray(chi_s, nr)), _p(_per_ray(chi_hi, nr)),
+                                     _p(_per_ray(chi_lo, nr)), float(kappa_scale),
+                                     float(delta_coeff), _p(_f64(fv)), int(max_steps),
+                                     int(threads), _p(kappa), _p(hsh), _p(ncr), _p(st))
+    return TraceResult(kappa, hsh, ncr, st, None)
+
+
+def cell_integral_k(Q, p1, h, direction, o, chis, chiA, chiB):
+    """One cell of the Method A gradient term (kernel 1 - 2 chi / chi_s)."""
+    return lib().rro_cell_integral_k(_p(_f64(Q)), _p(_f64(p1)), float(h), _p(_f64(direction)),
+                                     _p(_f64(o)), float(chis), float(chiA), float(chiB))
 
 
 def trace_adjoint_uniform(n, box, observer, dirs, chi_s, chi_hi, chi_lo, dl_dkappa,

@@ -72,6 +72,26 @@ double rro_cell_integral(const double* Q, const double* p1, double h, const doub
 /* The projection of T used as the integrand (Eqs. n1n1, n2n2, n1n2). */
 double rro_projection(const double* dir, const double* T, int32_t quantity);
 
+/* Method A (Eq. kappa2, Sec. IV C): vertex fields (delta, grad Phi) from
+ * the cell values (central differences of spacing h, mean of the eight
+ * incident cells); fv: n^3 x 4. */
+void rro_method_a_vertex_fields(int32_t n, int32_t open, double h, const double* phi,
+                                const double* delta, double* fv);
+/* Trace with the Method A integrand: delta_coeff * g * delta (delta_coeff in
+ * 1 / length^2 of the box unit, e.g. 3/2 Omega_m (H0/c)^2 / a) plus
+ * (n . grad Phi) dg/dchi, and the step's surface term -[g n . grad Phi]
+ * between chi_lo and chi_hi (Eqs. 2nterm, 2dterm2).  Kappa only. */
+int32_t rro_trace_uniform_method_a(int32_t n, int32_t open, double box, const double* observer,
+                                   int64_t n_rays, const double* dir, const double* chi_s,
+                                   const double* chi_hi, const double* chi_lo,
+                                   double kappa_scale, double delta_coeff, const double* fv,
+                                   int64_t max_steps, int32_t n_threads, double* kappa,
+                                   uint64_t* hash, int64_t* ncross, int32_t* status);
+/* One cell of the gradient term: int (1 - 2 chi / chi_s) Q dchi over the
+ * segment, Q trilinear from its eight vertex values (as rro_cell_integral). */
+double rro_cell_integral_k(const double* Q, const double* p1, double h, const double* dir,
+                           const double* o, double chis, double chiA, double chiB);
+
 /* Adjoint of kappa = A(Phi) for a uniform grid: dL/dPhi += A^T (dL/dkappa).
  * Explicit transpose of: per-cell integral -> vertex average -> FD stencil. */
 int32_t rro_trace_adjoint_uniform(int32_t n, double box, const double* observer,
