@@ -92,7 +92,7 @@ def lightcone_leg(args, api, I, torch, dev):
     nray = args.rays
     fov = math.radians(5.0)
     log(f"light cone: {n}^3 lognormal potential, {nray}^2 rays, {args.segments} segments")
-    phi0 = I.config2_phi0(n, box)
+    delta0, phi0 = I.config2_fields(n, box)
     segs = I.lightcone_segments(args.segments)
     chi_s = I.chi_of_z(1.0)
     dirs = I.fov_directions((0.0, 0.0, 1.0), fov, fov, nray, nray)
@@ -157,6 +157,10 @@ def lightcone_leg(args, api, I, torch, dev):
         t.close()
         del kap, comp, st
         torch.cuda.empty_cache()
+    if not args.no_method_a:
+        results["method_a"] = method_a_leg(args, api, I, torch, dev, delta0, grids, segs,
+                                           bundles, obs, results)
+    del delta0
     if args.copy_probe_mib:
         nb = args.copy_probe_mib * (1 << 20)
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
@@ -169,6 +173,55 @@ def lightcone_leg(args, api, I, torch, dev):
         del src, dst
     ctx = dict(phis=phis, segs=segs, dirs=dirs, chi_s=chi_s, box=box, obs=obs, n=n)
     return results, ctx
+
+
+def method_a_leg(args, api, I, torch, dev, delta0, grids, segs, bundles, obs, results):
+    """The same light cone with Method A (Eq. kappa2): per segment the vertex
+    fields (c delta, grad Phi) and the march with the density and gradient
+    kernels plus the segment's surface term; compared with Method B's map."""
+    box = grids[0].box
+    nr = bundles[0][0].n_rays
+    dd = torch.as_tensor(delta0.astype(np.float32), device=dev)
+    gd = api.Grid(dd, box, field="delta")
+    t = api.TidalTensor(gd, "fp32")
+    kap = torch.zeros(nr, dtype=torch.float32, device=dev)
+    comp = torch.zeros(nr, dtype=torch.float32, device=dev)
+    st = torch.zeros(nr, dtype=torch.int32, device=dev)
+    c0 = I.poisson_coefficient()
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in segs]
+
+    def step():
+        kap.zero_()
+        comp.zero_()
+        for k, (_, _, sk) in enumerate(segs):
+            ev[k][0].record(stream)
+            t.build_method_a(gd, grids[k], c0 * sk)
+            ev[k][1].record(stream)
+            api.trace(api_plan[0], t, bundles[k], obs, kappa=kap, kappa_comp=comp, status=st,
+                      persistent=0)
+            ev[k][2].record(stream)
+
+    api_plan = [api.Plan()]
+    step_ms = timed(step, args.steps, args.warmup, "light cone fp32 Method A")
+    build_ms = sum(e[0].elapsed_time(e[1]) for e in ev)
+    march_ms = sum(e[1].elapsed_time(e[2]) for e in ev)
+    ka = kap.double().cpu().numpy()
+    kb = results["fp32"]["kappa"]
+    t.close()
+    del dd, kap, comp
+    torch.cuda.empty_cache()
+    cross = results["fp32"]["cross"]
+    return {"workload": "the light cone with Method A (density and gradient terms, surface "
+                        "term per segment), FP32-Kahan",
+            "crossings_per_s": cross / (step_ms * 1e-3), "ms_per_step": step_ms,
+            "fields_build_ms_per_segment": build_ms / len(segs),
+            "march_crossings_per_s": cross / (march_ms * 1e-3),
+            "all_rays_ok": bool((st == 0).all().item()),
+            "kappa_vs_method_b": {
+                "rms_diff_over_rms_kappa": float(np.sqrt(np.mean((ka - kb) ** 2))
+                                                 / np.sqrt(np.mean(kb ** 2))),
+                "correlation": float(np.corrcoef(ka, kb)[0, 1])}}
 
 
 def amr_leg(args, api, I, torch, dev):
@@ -319,6 +372,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-method-a", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the AMR leg's autotuning")
     ap.add_argument("--tune-lightcone", action="store_true",
                     help="autotune the light-cone launch shape per segment (default: one "
@@ -335,7 +389,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.profile_steps:
-        args.no_fp64 = args.no_cpu = args.no_amr = True
+        args.no_fp64 = args.no_cpu = args.no_amr = args.no_method_a = True
 
     import torch
     from paper_1601_02012_amd import api, inputs as I
@@ -392,6 +446,8 @@ def main():
         "tuned_shapes": sorted(set(r32["shapes"])),
         "all_rays_ok": r32["status_ok"],
     }
+    if "method_a" in results:
+        out["method_a"] = results["method_a"]
     if "fp32_box" in results:
         rb = results["fp32_box"]
         box = {"value": rb["cross"] / (rb["step_ms"] * 1e-3), "unit": "crossings/s",

@@ -64,8 +64,10 @@ typedef enum {
 } rr_status;
 
 typedef enum { RR_GRID_UNIFORM = 0, RR_GRID_OCTREE = 1 } rr_grid_kind;
-/* RR_FIELD_DELTA (the density term of the paper's Method A, Eq. kappa2) is
- * accepted by the descriptor but returns RR_ERR_UNSUPPORTED. */
+/* RR_FIELD_PHI: the potential (Method B, Eq. kappa; also Method A's gradient
+ * term).  RR_FIELD_DELTA: the density contrast of Method A's Poisson term
+ * (Eq. kappa2), uniform grids only; a tensor created from it holds Method A
+ * vertex fields (rr_build_method_a_fields). */
 typedef enum { RR_FIELD_PHI = 0, RR_FIELD_DELTA = 1 } rr_field_kind;
 /* PERIODIC: the grid is one period of a replicated box (the paper's tiled
  * boxes, Sec. III B, with one realization).  OPEN: no wrap; cells on the two
@@ -136,6 +138,23 @@ rr_status rr_tensor_destroy(rr_tensor t);
  * at rr_tensor_create; values may change between calls (one call per N-body
  * step).  Asynchronous on s; no allocation. */
 rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s);
+
+/* Method A (Sec. IV C, Eq. kappa2): kappa from the density contrast and the
+ * potential's gradient instead of the tidal tensor.  The tensor is created
+ * from a density descriptor (field RR_FIELD_DELTA, uniform grids only) and
+ * holds per vertex (delta_coeff delta, dPhi/dx, dPhi/dy, dPhi/dz): cell
+ * values of delta, gradients by central differences, both averaged over the
+ * eight incident cells (Sec. III F).  delta_coeff multiplies delta into the
+ * Laplacian of phi's units, in 1 / length^2 of the box unit (for phi = Phi/c^2:
+ * 3/2 Omega_m (H0/c)^2 / a).  rr_trace_rays then adds, per ray and chi
+ * segment, int g delta_coeff delta + int (n . grad phi) dg/dchi (kernel
+ * 1 - 2 chi / chi_s) and the segment's surface term -[g n . grad phi] from
+ * chi_lo to chi_hi (Eqs. 2nterm, 2dterm2); the term with the time derivative
+ * of the potential is left out, as in the paper.  Kappa and the trilinear
+ * integral only (RR_ERR_UNSUPPORTED otherwise); delta and phi share the grid
+ * and dtype of the tensor.  Asynchronous on s; no allocation. */
+rr_status rr_build_method_a_fields(rr_tensor t, const rr_field_desc* delta,
+                                   const rr_field_desc* phi, double delta_coeff, rr_stream s);
 
 /* Cell-centre tidal tensor (Eq. tidalexample, the cell's own level) for the
  * nearest-grid-point integral (Eq. Iclensing_ngp): uniform tensors then hold

@@ -53,6 +53,8 @@ SIGNATURES = [
     ("rr_tensor_destroy", _i32, [_vp]),
     ("rr_build_tidal_tensor", _i32, [_vp, C.POINTER(FieldDesc), _vp]),
     ("rr_build_tidal_tensor_centres", _i32, [_vp, C.POINTER(FieldDesc), _vp]),
+    ("rr_build_method_a_fields", _i32, [_vp, C.POINTER(FieldDesc), C.POINTER(FieldDesc),
+                                        C.c_double, _vp]),
     ("rr_build_tidal_tensor_box", _i32, [_vp, C.POINTER(FieldDesc), C.POINTER(_i32),
                                          C.POINTER(_i32), _vp]),
     ("rr_tensor_layout", _i32, [_vp, C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_i32),

@@ -49,7 +49,7 @@ class Grid:
 
     def __init__(self, values: torch.Tensor, box: float, *, n_base: Optional[int] = None,
                  boundary: str = "periodic", child_oct: Optional[torch.Tensor] = None,
-                 max_level: int = 0):
+                 max_level: int = 0, field: str = "phi"):
         if values.dtype not in (torch.float32, torch.float64):
             raise TypeError("values must be float32 or float64")
         self.values = values.contiguous()
@@ -64,11 +64,14 @@ class Grid:
             self.n = int(values.shape[0]) if n_base is None else int(n_base)
         self.boundary = A.BOUNDARY_OPEN if boundary == "open" else A.BOUNDARY_PERIODIC
         self.max_level = int(max_level)
+        if field not in ("phi", "delta"):
+            raise ValueError("field is 'phi' (potential) or 'delta' (density contrast)")
+        self.field = A.FIELD_DELTA if field == "delta" else A.FIELD_PHI
 
     def desc(self) -> A.FieldDesc:
         d = A.FieldDesc()
         d.kind = A.GRID_OCTREE if self.octree else A.GRID_UNIFORM
-        d.field = A.FIELD_PHI
+        d.field = self.field
         d.boundary = self.boundary
         d.dtype = A.F32 if self.values.dtype == torch.float32 else A.F64
         d.n_base = self.n
@@ -97,6 +100,16 @@ class TidalTensor:
         d = g.desc()
         A.check("rr_build_tidal_tensor",
                 _lib.rr_build_tidal_tensor(self.handle, C.byref(d), _stream(stream)))
+        return self
+
+    def build_method_a(self, delta: Grid, phi: Grid, delta_coeff: float,
+                       stream=None) -> "TidalTensor":
+        """rr_build_method_a_fields: (delta_coeff delta, grad phi) vertex fields of a
+        tensor created from a density grid (Method A, Eq. kappa2)."""
+        dd, dp = delta.desc(), phi.desc()
+        A.check("rr_build_method_a_fields",
+                _lib.rr_build_method_a_fields(self.handle, C.byref(dd), C.byref(dp),
+                                              float(delta_coeff), _stream(stream)))
         return self
 
     def build_centres(self, grid: Optional[Grid] = None, stream=None) -> "TidalTensor":

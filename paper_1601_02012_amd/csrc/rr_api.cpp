@@ -53,7 +53,9 @@ struct rr_tensor_s {
   int64_t n_records = 0;
   int32_t record_bytes = 0;
   void* grad = nullptr;        // adjoint workspace (allocated on first use)
-  int32_t content = 0;         // uniform records: 0 unbuilt, 1 vertex tensors, 2 cell centres
+  int32_t content = 0;         // uniform records: 0 unbuilt, 1 vertex tensors, 2 cell centres,
+                               // 3 Method A vertex fields
+  int32_t method_a = 0;        // created from a density field: (c delta, grad Phi) records
   std::unique_ptr<rr::OctreeTensor> oct;
 };
 
@@ -101,9 +103,10 @@ rr_status validate_field(const rr_field_desc* f) {
   if (!f) return fail(RR_ERR_INVALID_ARG, "field descriptor is NULL");
   if (f->kind != RR_GRID_UNIFORM && f->kind != RR_GRID_OCTREE)
     return fail(RR_ERR_INVALID_ARG, "unknown grid kind %d", f->kind);
-  if (f->field == RR_FIELD_DELTA)
-    return fail(RR_ERR_UNSUPPORTED, "density fields (Method A) are not implemented");
-  if (f->field != RR_FIELD_PHI) return fail(RR_ERR_INVALID_ARG, "unknown field kind %d", f->field);
+  if (f->field != RR_FIELD_PHI && f->field != RR_FIELD_DELTA)
+    return fail(RR_ERR_INVALID_ARG, "unknown field kind %d", f->field);
+  if (f->field == RR_FIELD_DELTA && f->kind != RR_GRID_UNIFORM)
+    return fail(RR_ERR_UNSUPPORTED, "Method A (density fields) is implemented for uniform grids");
   if (f->dtype != RR_F32 && f->dtype != RR_F64)
     return fail(RR_ERR_INVALID_ARG, "unknown dtype %d", f->dtype);
   if (f->boundary != RR_BOUNDARY_PERIODIC && f->boundary != RR_BOUNDARY_OPEN)
@@ -153,7 +156,8 @@ rr_status rr_tensor_create(const rr_field_desc* f, rr_precision p, rr_tensor* ou
   t->box = f->box_size;
   if (f->kind == RR_GRID_UNIFORM) {
     const int64_t nv = (int64_t)f->n_base * f->n_base * f->n_base;
-    t->record_bytes = p == RR_PREC_FP32_KAHAN ? 24 : 48;
+    t->method_a = f->field == RR_FIELD_DELTA;
+    t->record_bytes = (t->method_a ? 4 : 6) * (p == RR_PREC_FP32_KAHAN ? 4 : 8);
     t->n_records = nv;
     hipError_t e = hipMalloc(&t->data, (size_t)nv * t->record_bytes);
     if (e != hipSuccess) return fail(RR_ERR_OOM, "vertex tensor: %s", hipGetErrorString(e));
@@ -189,6 +193,9 @@ rr_status rr_tensor_layout(rr_tensor t, const void** data, int64_t* n_records,
 
 rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s) {
   if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  if (t->method_a || (f && f->field != RR_FIELD_PHI))
+    return fail(RR_ERR_INVALID_ARG, "tidal tensors are built from potentials (Method A: "
+                                    "rr_build_method_a_fields)");
   rr_status st = validate_field(f);
   if (st != RR_OK) return st;
   if (f->kind != t->kind || f->n_base != t->n || f->boundary != t->boundary)
@@ -211,6 +218,8 @@ rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s
 rr_status rr_build_tidal_tensor_box(rr_tensor t, const rr_field_desc* f, const int32_t lo[3],
                                      const int32_t size[3], rr_stream s) {
   if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  if (t->method_a || (f && f->field != RR_FIELD_PHI))
+    return fail(RR_ERR_INVALID_ARG, "tidal tensors are built from potentials");
   if (!lo || !size) return fail(RR_ERR_INVALID_ARG, "box pointers are NULL");
   rr_status st = validate_field(f);
   if (st != RR_OK) return st;
@@ -239,6 +248,8 @@ rr_status rr_build_tidal_tensor_box(rr_tensor t, const rr_field_desc* f, const i
 
 rr_status rr_build_tidal_tensor_centres(rr_tensor t, const rr_field_desc* f, rr_stream s) {
   if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  if (t->method_a || (f && f->field != RR_FIELD_PHI))
+    return fail(RR_ERR_INVALID_ARG, "tidal tensors are built from potentials");
   rr_status st = validate_field(f);
   if (st != RR_OK) return st;
   if (f->kind != t->kind || f->n_base != t->n || f->boundary != t->boundary)
@@ -249,6 +260,34 @@ rr_status rr_build_tidal_tensor_centres(rr_tensor t, const rr_field_desc* f, rr_
                                           (hipStream_t)s),
          "centre tensor launch");
   t->content = 2;
+  return RR_OK;
+}
+
+rr_status rr_build_method_a_fields(rr_tensor t, const rr_field_desc* delta,
+                                   const rr_field_desc* phi, double delta_coeff, rr_stream s) {
+  if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  if (!t->method_a)
+    return fail(RR_ERR_INVALID_ARG, "the tensor was created from a potential (Method B)");
+  rr_status st = validate_field(delta);
+  if (st != RR_OK) return st;
+  st = validate_field(phi);
+  if (st != RR_OK) return st;
+  if (delta->field != RR_FIELD_DELTA || phi->field != RR_FIELD_PHI)
+    return fail(RR_ERR_INVALID_ARG, "need a density field and a potential");
+  for (const rr_field_desc* f : {delta, phi})
+    if (f->kind != RR_GRID_UNIFORM || f->n_base != t->n || f->boundary != t->boundary ||
+        f->box_size != t->box)
+      return fail(RR_ERR_INVALID_ARG, "field does not match the grid the tensor was created for");
+  if (delta->dtype != phi->dtype)
+    return fail(RR_ERR_INVALID_ARG, "density and potential must share a dtype");
+  if (!std::isfinite(delta_coeff)) return fail(RR_ERR_NONFINITE, "delta_coeff is not finite");
+  const double h0 = t->box / (double)t->n;
+  RR_HIP(rr::launch_method_a_vertex_fields(t->precision, phi->dtype, t->n,
+                                           t->boundary == RR_BOUNDARY_OPEN, delta->values,
+                                           phi->values, delta_coeff * h0 * h0, t->data,
+                                           (hipStream_t)s),
+         "Method A fields launch");
+  t->content = 3;
   return RR_OK;
 }
 
@@ -298,8 +337,11 @@ rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle
     return fail(RR_ERR_INVALID_ARG, "unknown quantity %d", tp->quantity);
   if (tp->integral != RR_INTEGRAL_TRILINEAR && tp->integral != RR_INTEGRAL_NGP)
     return fail(RR_ERR_INVALID_ARG, "unknown integral %d", tp->integral);
-  if (t->kind == RR_GRID_UNIFORM && t->content != 0 &&
-      t->content != (tp->integral == RR_INTEGRAL_NGP ? 2 : 1))
+  if (t->method_a) {
+    if (tp->quantity != RR_Q_KAPPA || tp->integral != RR_INTEGRAL_TRILINEAR)
+      return fail(RR_ERR_UNSUPPORTED, "Method A gives kappa with the trilinear integral only");
+  } else if (t->kind == RR_GRID_UNIFORM && t->content != 0 &&
+             t->content != (tp->integral == RR_INTEGRAL_NGP ? 2 : 1))
     return fail(RR_ERR_INVALID_ARG,
                 tp->integral == RR_INTEGRAL_NGP
                     ? "the NGP integral reads cell-centre records (rr_build_tidal_tensor_centres)"
@@ -600,6 +642,7 @@ rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const 
   a.open = t->boundary == RR_BOUNDARY_OPEN;
   a.quantity = tp->quantity;
   a.integral = tp->integral;
+  a.mode = t->method_a ? 2 : (tp->integral == RR_INTEGRAL_NGP ? 1 : 0);
   a.max_crossings = tp->max_crossings;
   a.kappa = kappa;
   a.kappa_comp = kappa_comp;
@@ -639,8 +682,10 @@ rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
     return fail(RR_ERR_UNSUPPORTED, "the adjoint is implemented for periodic grids only");
   if (t->precision != RR_PREC_FP32_KAHAN || f->dtype != RR_F32)
     return fail(RR_ERR_UNSUPPORTED, "the adjoint takes an FP32 field and an FP32 tensor");
-  if (tp->quantity != RR_Q_KAPPA)
-    return fail(RR_ERR_UNSUPPORTED, "the adjoint is implemented for kappa only");
+  if (tp->quantity != RR_Q_KAPPA || tp->integral != RR_INTEGRAL_TRILINEAR || t->method_a)
+    return fail(RR_ERR_UNSUPPORTED,
+                "the adjoint is implemented for Method B kappa with the trilinear integral");
+  if (f->field != RR_FIELD_PHI) return fail(RR_ERR_INVALID_ARG, "the adjoint needs a potential");
   if (f->n_base != t->n) return fail(RR_ERR_INVALID_ARG, "field and tensor grids differ");
   if (!dl_dkappa || !dl_dphi) return fail(RR_ERR_INVALID_ARG, "gradient pointers are NULL");
   const hipStream_t hs = (hipStream_t)s;

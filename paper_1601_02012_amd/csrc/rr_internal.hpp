@@ -30,6 +30,7 @@ struct TraceArgs {
   int32_t open;              // RR_BOUNDARY_OPEN
   int32_t quantity;
   int32_t integral;
+  int32_t mode;              // integrand: 0 tidal tensor, 1 tidal tensor at centres (NGP), 2 Method A
   int64_t max_crossings;
   // outputs
   void* kappa;
@@ -60,6 +61,10 @@ struct VertexRecord<double> {
 hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int open, const int* lo,
                                         const int* size, const void* phi, void* tv,
                                         hipStream_t s);
+// Method A vertex records (c delta, grad Phi): 4 components per vertex
+hipError_t launch_method_a_vertex_fields(int precision, int dtype, int n, int open,
+                                         const void* delta, const void* phi, double cdelta,
+                                         void* fv, hipStream_t s);
 // cell-centre tensor records (one per cell, same layout as the vertex records)
 hipError_t launch_centre_tensor_uniform(int precision, int dtype, int n, int open,
                                         const void* phi, void* tc, hipStream_t s);

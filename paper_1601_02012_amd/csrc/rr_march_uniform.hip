@@ -49,25 +49,79 @@ __device__ __forceinline__ R project(const R* __restrict__ tv, Off off, const R*
   return acc;
 }
 
+// Integrand modes: the tidal tensor with the trilinear integral, the tidal
+// tensor at cell centres (NGP), and Method A's (c delta, grad Phi) fields.
+constexpr int kTidal = 0, kNgp = 1, kMethodA = 2;
+
+// Corner value(s) of the record at `off`: Q = P : T (tidal modes), or
+// (c delta, n . grad Phi) with P[0..2] = n (Method A).
+template <typename R, typename Off, int kMode>
+__device__ __forceinline__ void corner_value(const R* __restrict__ tv, Off off, const R* P, R& q,
+                                             R& q2) {
+  if constexpr (kMode == kMethodA) {
+    const char* b = reinterpret_cast<const char*>(tv) + (uint64_t)off;
+    R t[4];
+    if constexpr (sizeof(R) == 4) {
+      const float4 x = *reinterpret_cast<const float4*>(b);
+      t[0] = x.x; t[1] = x.y; t[2] = x.z; t[3] = x.w;
+    } else {
+      const double2* p = reinterpret_cast<const double2*>(b);
+      const double2 x = p[0], y = p[1];
+      t[0] = x.x; t[1] = x.y; t[2] = y.x; t[3] = y.y;
+    }
+    q = t[0];
+    q2 = fma(P[2], t[3], fma(P[1], t[2], P[0] * t[1]));
+  } else {
+    q = project<R, Off>(tv, off, P);
+    q2 = (R)0;
+  }
+}
+
 // All eight corners (c = b0 + 2 b1 + 4 b2), loaded in two halves so that at
 // most four vertex records are in flight: this path runs only at the start of
 // a ray and after edge or vertex crossings, and must not set the register
 // budget of the whole loop.
-template <typename R, typename Off>
+template <typename R, typename Off, int kMode>
 __device__ __forceinline__ void load_corners(const R* __restrict__ tv, Off base, const Off* dX,
-                                             const R* P, R* q) {
+                                             const R* P, R* q, R* q2) {
   const Off v2 = base + dX[1];
-  q[0] = project<R, Off>(tv, base, P);
-  q[1] = project<R, Off>(tv, base + dX[0], P);
-  q[2] = project<R, Off>(tv, v2, P);
-  q[3] = project<R, Off>(tv, v2 + dX[0], P);
+  corner_value<R, Off, kMode>(tv, base, P, q[0], q2[0]);
+  corner_value<R, Off, kMode>(tv, base + dX[0], P, q[1], q2[1]);
+  corner_value<R, Off, kMode>(tv, v2, P, q[2], q2[2]);
+  corner_value<R, Off, kMode>(tv, v2 + dX[0], P, q[3], q2[3]);
   __builtin_amdgcn_sched_barrier(0);
   const Off v4 = base + dX[2];
   const Off v6 = v4 + dX[1];
-  q[4] = project<R, Off>(tv, v4, P);
-  q[5] = project<R, Off>(tv, v4 + dX[0], P);
-  q[6] = project<R, Off>(tv, v6, P);
-  q[7] = project<R, Off>(tv, v6 + dX[0], P);
+  corner_value<R, Off, kMode>(tv, v4, P, q[4], q2[4]);
+  corner_value<R, Off, kMode>(tv, v4 + dX[0], P, q[5], q2[5]);
+  corner_value<R, Off, kMode>(tv, v6, P, q[6], q2[6]);
+  corner_value<R, Off, kMode>(tv, v6 + dX[0], P, q[7], q2[7]);
+}
+
+// One face crossed along axis k (one-hot k0, k1, k2 = neither): the four
+// values of that face move to the entry face, the four of the new exit face
+// F_j (j = i_a + 2 i_b over the two other axes a < b) come in (Method A's two
+// corner sets; the tidal path writes the same selects inline).  The selects
+// operate on register values: the empty asm statements keep the compiler
+// from turning a select of two array elements into an indexed load, which
+// would move the array to LDS.
+template <typename R>
+__device__ __forceinline__ void shift_face(R* q, bool k0, bool k1, R F0, R F1, R F2, R F3) {
+  R a[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    a[c] = q[c];
+    asm volatile("" : "+v"(a[c]));
+  }
+  const R n0 = k0 ? a[1] : (k1 ? a[2] : a[4]);
+  const R n1 = k0 ? F0 : (k1 ? a[3] : a[5]);
+  const R n2 = k0 ? a[3] : (k1 ? F0 : a[6]);
+  const R n3 = k0 || k1 ? F1 : a[7];
+  const R n4 = k0 ? a[5] : (k1 ? a[6] : F0);
+  const R n5 = k0 ? F2 : (k1 ? a[7] : F1);
+  const R n6 = k0 ? a[7] : F2;
+  q[0] = n0; q[1] = n1; q[2] = n2; q[3] = n3;
+  q[4] = n4; q[5] = n5; q[6] = n6; q[7] = F3;
 }
 
 // One ray, in the ray's own frame: along each axis, corner bit 0 is the
@@ -84,7 +138,7 @@ __device__ __forceinline__ void load_corners(const R* __restrict__ tv, Off base,
 // wrapped index of the exit vertex layer; the cell's entry corner is one byte
 // offset into the vertex array (32 bit when the tensor is below 4 GiB), with
 // per-axis steps to the exit layer (modular arithmetic).
-template <typename R, bool kDebug, typename Off, bool kNgp>
+template <typename R, bool kDebug, typename Off, int kMode>
 __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const DevBundle& B,
                           int64_t ray) {
   const int64_t out = B.ray_offset + ray;
@@ -97,7 +151,10 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     return;
   }
   R P[6];
-  {
+  if constexpr (kMode == kMethodA) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) P[c] = (R)d[c];
+  } else {
     double Pd[6];
     projection(a.quantity, d[0], d[1], d[2], Pd);
 #pragma unroll
@@ -105,7 +162,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   }
 
   const int n = a.n;
-  constexpr Off kRec = (Off)(6 * sizeof(R));  // bytes per vertex record
+  constexpr Off kRec = (Off)((kMode == kMethodA ? 4 : 6) * sizeof(R));  // bytes per record
   const Off stride[3] = {kRec, kRec * (Off)n, kRec * (Off)n * (Off)n};
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
@@ -144,8 +201,8 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
 #pragma unroll
   for (int k = 0; k < 3; ++k) fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
 
-  R q[8];  // corner values, corner c = b0 + 2 b1 + 4 b2 in the ray frame
-  if constexpr (!kNgp) load_corners<R, Off>(tv, base, dX, P, q);
+  R q[8], q2[8];  // corner values (q2: Method A's gradient term), c = b0 + 2 b1 + 4 b2
+  if constexpr (kMode != kNgp) load_corners<R, Off, kMode>(tv, base, dX, P, q, q2);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
@@ -194,7 +251,25 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     for (int k = 0; k < 3; ++k) fB[k] = (R)1 - absd[k] * (R)(chiB - te[k]);
     const R L = (R)(chiA - chiB);
     R ic;
-    if constexpr (kNgp) {
+    if constexpr (kMode == kMethodA) {
+      // Eq. (kappa2): c delta against g, n . grad Phi against dg/dchi, and the
+      // step's surface term -[g n . grad Phi] at its first and last point
+      R s = cell_integral_a<R>(q, q2, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis);
+      const bool first = count == 0, last = chiB == lo;
+      if (first || last) {
+        R dq[4];
+        dq[0] = q2[1] - q2[0]; dq[1] = q2[3] - q2[2]; dq[2] = q2[5] - q2[4]; dq[3] = q2[7] - q2[6];
+        if (first) {
+          const R g = (R)chiA * (R)(B.chi_s - chiA) * inv_chis;
+          s -= g * trilerp<R>(q2, dq, fA[0], fA[1], fA[2]);
+        }
+        if (last) {
+          const R g = (R)chiB * (R)(B.chi_s - chiB) * inv_chis;
+          s += g * trilerp<R>(q2, dq, fB[0], fB[1], fB[2]);
+        }
+      }
+      ic = s * scale;
+    } else if constexpr (kMode == kNgp) {
       // Eq. (Iclensing_ngp): the cell-centre value times the integral of g over
       // the piece, L (g(mid) - L^2 / (12 chi_s)) with g(chi) = chi (chi_s - chi) / chi_s
       Off cellv = base;
@@ -251,7 +326,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
         }
       }
     }
-    if constexpr (kNgp) {
+    if constexpr (kMode == kNgp) {
       // one record per cell: nothing carried from cell to cell
     } else if ((int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1) {
       // one face crossed (axis k): keep its four values, load the new exit face,
@@ -261,21 +336,31 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
       const Off da = k0 ? dX[1] : dX[0];
       const Off db = k0 || k1 ? dX[2] : dX[1];
       const Off w0 = base + dk, w1 = w0 + da;
-      const R F0 = project<R, Off>(tv, w0, P);
-      const R F1 = project<R, Off>(tv, w1, P);
-      const R F2 = project<R, Off>(tv, w0 + db, P);
-      const R F3 = project<R, Off>(tv, w1 + db, P);
-      const R n0 = k0 ? q[1] : (k1 ? q[2] : q[4]);
-      const R n1 = k0 ? F0 : (k1 ? q[3] : q[5]);
-      const R n2 = k0 ? q[3] : (k1 ? F0 : q[6]);
-      const R n3 = k0 || k1 ? F1 : q[7];
-      const R n4 = k0 ? q[5] : (k1 ? q[6] : F0);
-      const R n5 = k0 ? F2 : (k1 ? q[7] : F1);
-      const R n6 = k0 ? q[7] : F2;
-      q[0] = n0; q[1] = n1; q[2] = n2; q[3] = n3;
-      q[4] = n4; q[5] = n5; q[6] = n6; q[7] = F3;
+      if constexpr (kMode == kMethodA) {
+        R F[4], G[4];
+        corner_value<R, Off, kMode>(tv, w0, P, F[0], G[0]);
+        corner_value<R, Off, kMode>(tv, w1, P, F[1], G[1]);
+        corner_value<R, Off, kMode>(tv, w0 + db, P, F[2], G[2]);
+        corner_value<R, Off, kMode>(tv, w1 + db, P, F[3], G[3]);
+        shift_face<R>(q, k0, k1, F[0], F[1], F[2], F[3]);
+        shift_face<R>(q2, k0, k1, G[0], G[1], G[2], G[3]);
+      } else {
+        const R F0 = project<R, Off>(tv, w0, P);
+        const R F1 = project<R, Off>(tv, w1, P);
+        const R F2 = project<R, Off>(tv, w0 + db, P);
+        const R F3 = project<R, Off>(tv, w1 + db, P);
+        const R n0 = k0 ? q[1] : (k1 ? q[2] : q[4]);
+        const R n1 = k0 ? F0 : (k1 ? q[3] : q[5]);
+        const R n2 = k0 ? q[3] : (k1 ? F0 : q[6]);
+        const R n3 = k0 || k1 ? F1 : q[7];
+        const R n4 = k0 ? q[5] : (k1 ? q[6] : F0);
+        const R n5 = k0 ? F2 : (k1 ? q[7] : F1);
+        const R n6 = k0 ? q[7] : F2;
+        q[0] = n0; q[1] = n1; q[2] = n2; q[3] = n3;
+        q[4] = n4; q[5] = n5; q[6] = n6; q[7] = F3;
+      }
     } else {
-      load_corners<R, Off>(tv, base, dX, P, q);
+      load_corners<R, Off, kMode>(tv, base, dX, P, q, q2);
     }
     chiA = chiB;
   }
@@ -293,7 +378,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   }
 }
 
-template <typename R, bool kDebug, typename Off, bool kNgp>
+template <typename R, bool kDebug, typename Off, int kMode>
 __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -301,7 +386,7 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Off, kNgp>(tv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Off, kMode>(tv, a, B, (int64_t)iy * B.nx + ix);
 }
 
 // One wavefront per tile.  Workgroups are dealt round-robin to the 8 XCDs;
@@ -309,7 +394,7 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
 // is held to 96 VGPRs (5 wavefronts per SIMD): the march waits on dependent
 // gathers, and the fifth wavefront hides more of that latency than the
 // compiler's unconstrained schedule (100 VGPRs, 4 wavefronts) gains.
-template <typename R, bool kDebug, typename Off, bool kNgp>
+template <typename R, bool kDebug, typename Off, int kMode>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
 void march_uniform_kernel(const R* __restrict__ tv,
                                                             TraceArgs a) {
@@ -323,12 +408,12 @@ void march_uniform_kernel(const R* __restrict__ tv,
   // the tile is the same for the 64 lanes: keep it (and the bundle) scalar
   const int64_t tile = vblk * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
-  run_tile<R, kDebug, Off, kNgp>(tv, a, tile, lane);
+  run_tile<R, kDebug, Off, kMode>(tv, a, tile, lane);
 }
 
 // Persistent workgroups: every wavefront pulls tiles from a device counter
 // until the queue is drained (every wave reaches the exit test).
-template <typename R, bool kDebug, typename Off, bool kNgp>
+template <typename R, bool kDebug, typename Off, int kMode>
 __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restrict__ tv,
                                                                 TraceArgs a) {
   const int lane = threadIdx.x & 63;
@@ -340,7 +425,7 @@ __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restr
     const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
     if (tile >= a.n_tiles) break;
-    run_tile<R, kDebug, Off, kNgp>(tv, a, tile, lane);
+    run_tile<R, kDebug, Off, kMode>(tv, a, tile, lane);
   }
 }
 
@@ -391,19 +476,19 @@ __global__ __launch_bounds__(256) void ray_bounds_kernel(TraceArgs a, int* out) 
   }
 }
 
-template <typename R, bool kDebug, typename Off, bool kNgp>
+template <typename R, bool kDebug, typename Off, int kMode>
 hipError_t launch3(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
                    hipStream_t s) {
   const int wpb = block / 64;
   if (persistent) {
     const int blocks = (grid_waves + wpb - 1) / wpb;
-    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Off, kNgp>), dim3(blocks), dim3(block), 0, s,
+    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Off, kMode>), dim3(blocks), dim3(block), 0, s,
                        (const R*)tv, a);
   } else {
     int64_t blocks = (a.n_tiles + wpb - 1) / wpb;
     if (blocks == 0) return hipSuccess;
     blocks = (blocks + 7) / 8 * 8;   // the XCD remap is a bijection on multiples of 8
-    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Off, kNgp>), dim3((unsigned)blocks), dim3(block),
+    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Off, kMode>), dim3((unsigned)blocks), dim3(block),
                        0, s, (const R*)tv, a);
   }
   return hipGetLastError();
@@ -414,19 +499,27 @@ hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block,
                   hipStream_t s) {
   const bool dbg = a.hash || a.log || a.count;
   // 32-bit byte offsets when the whole tensor is below 4 GiB
-  const bool small = (int64_t)a.n * a.n * a.n * (int64_t)(6 * sizeof(R)) < (1ll << 32);
-  if (a.integral == RR_INTEGRAL_NGP) {
+  const int words = a.mode == kMethodA ? 4 : 6;
+  const bool small = (int64_t)a.n * a.n * a.n * (int64_t)(words * sizeof(R)) < (1ll << 32);
+  if (a.mode == kMethodA) {
     if (dbg)
-      return small ? launch3<R, true, uint32_t, true>(tv, a, persistent, block, grid_waves, s)
-                   : launch3<R, true, uint64_t, true>(tv, a, persistent, block, grid_waves, s);
-    return small ? launch3<R, false, uint32_t, true>(tv, a, persistent, block, grid_waves, s)
-                 : launch3<R, false, uint64_t, true>(tv, a, persistent, block, grid_waves, s);
+      return small ? launch3<R, true, uint32_t, kMethodA>(tv, a, persistent, block, grid_waves, s)
+                   : launch3<R, true, uint64_t, kMethodA>(tv, a, persistent, block, grid_waves, s);
+    return small ? launch3<R, false, uint32_t, kMethodA>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, false, uint64_t, kMethodA>(tv, a, persistent, block, grid_waves, s);
+  }
+  if (a.mode == kNgp) {
+    if (dbg)
+      return small ? launch3<R, true, uint32_t, kNgp>(tv, a, persistent, block, grid_waves, s)
+                   : launch3<R, true, uint64_t, kNgp>(tv, a, persistent, block, grid_waves, s);
+    return small ? launch3<R, false, uint32_t, kNgp>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, false, uint64_t, kNgp>(tv, a, persistent, block, grid_waves, s);
   }
   if (dbg)
-    return small ? launch3<R, true, uint32_t, false>(tv, a, persistent, block, grid_waves, s)
-                 : launch3<R, true, uint64_t, false>(tv, a, persistent, block, grid_waves, s);
-  return small ? launch3<R, false, uint32_t, false>(tv, a, persistent, block, grid_waves, s)
-               : launch3<R, false, uint64_t, false>(tv, a, persistent, block, grid_waves, s);
+    return small ? launch3<R, true, uint32_t, kTidal>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, true, uint64_t, kTidal>(tv, a, persistent, block, grid_waves, s);
+  return small ? launch3<R, false, uint32_t, kTidal>(tv, a, persistent, block, grid_waves, s)
+               : launch3<R, false, uint64_t, kTidal>(tv, a, persistent, block, grid_waves, s);
 }
 
 }  // namespace

@@ -688,7 +688,7 @@ hipError_t OctreeTensor::march(const TraceArgs& a, int persistent, int grid_wave
   if (a.n_tiles == 0) return hipSuccess;
   Tree T{child_oct_dev, reinterpret_cast<const int4*>(oct_info), n, (int64_t)n * n * n};
   const bool dbg = a.hash || a.log || a.count;
-  if (a.integral == RR_INTEGRAL_NGP) {   // cell-centre records, 6 per cell
+  if (a.mode == 1) {   // NGP: cell-centre records, 6 per cell
     if (precision == RR_PREC_FP32_KAHAN)
       return dbg ? launch_march<float, true, true>(T, centre, a, persistent, grid_waves, s)
                  : launch_march<float, false, true>(T, centre, a, persistent, grid_waves, s);

@@ -145,6 +145,33 @@ __device__ __forceinline__ R cell_integral(const R* q, const R* uA, const R* uB,
   return acc * L * inv_chis;
 }
 
+// Method A (Eq. kappa2) for one cell: int g (c delta) + (dg/dchi) (n . grad Phi)
+// over [chi_B, chi_A], both fields trilinear (qd, qg at the corners).  With
+// g = chi (chi_s - chi) / chi_s and dg/dchi = (chi_s - 2 chi) / chi_s the
+// integrand has degree <= 5: the same three-point rule is exact.
+template <typename R>
+__device__ __forceinline__ R cell_integral_a(const R* qd, const R* qg, const R* uA, const R* uB,
+                                             R L, R chiB, R DB, R inv_chis) {
+  R dd[4], dg[4];
+  dd[0] = qd[1] - qd[0]; dd[1] = qd[3] - qd[2]; dd[2] = qd[5] - qd[4]; dd[3] = qd[7] - qd[6];
+  dg[0] = qg[1] - qg[0]; dg[1] = qg[3] - qg[2]; dg[2] = qg[5] - qg[4]; dg[3] = qg[7] - qg[6];
+  const R du0 = uA[0] - uB[0], du1 = uA[1] - uB[1], du2 = uA[2] - uB[2];
+  const R cs[3] = {(R)GL3::c0, (R)GL3::c1, (R)GL3::c2};
+  const R ws[3] = {(R)GL3::w0, (R)GL3::w1, (R)GL3::w2};
+  R acc = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R c = cs[k];
+    const R u0 = fma(du0, c, uB[0]), u1 = fma(du1, c, uB[1]), u2 = fma(du2, c, uB[2]);
+    const R chik = fma(L, c, chiB);
+    const R rest = fma(-L, c, DB);               // chi_s - chi
+    const R vd = trilerp(qd, dd, u0, u1, u2);
+    const R vg = trilerp(qg, dg, u0, u1, u2);
+    acc = fma(ws[k], fma(chik * rest, vd, (rest - chik) * vg), acc);
+  }
+  return acc * L * inv_chis;
+}
+
 // FNV-1a, 64 bit, over the 8 little-endian bytes of w.
 __device__ __forceinline__ uint64_t fnv_word(uint64_t h, uint64_t w) {
 #pragma unroll

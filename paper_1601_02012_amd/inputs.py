@@ -252,9 +252,21 @@ def lightcone_segments(n_seg: int = 20, a_src: float = 0.5):
 
 
 def config2_phi0(n: int = 512, box: float = 1000.0) -> np.ndarray:
+    return config2_fields(n, box)[1]
+
+
+def config2_fields(n: int = 512, box: float = 1000.0):
+    """(delta0, phi0) of the light cone: the lognormal density contrast (mean
+    removed, the k = 0 mode the Poisson solve drops) and its Phi/c^2 at a = 1."""
     rf, *_ = seeds(2)
     delta = lognormal_delta(n, box, rf, slope=-2.0, sigma_g=1.0)
-    return poisson_phi(delta, box)
+    phi = poisson_phi(delta, box)
+    return delta - delta.mean(), phi
+
+
+def poisson_coefficient(a: float = 1.0) -> float:
+    """(3/2) Omega_m (H0/c)^2 / a in (Mpc/h)^-2: nabla^2 (Phi/c^2) = this x delta."""
+    return 1.5 * OMEGA_M / (C_OVER_H0 ** 2 * a)
 
 
 def config2(n: int = 512, box: float = 1000.0, nray: int = 2048, fov_deg: float = 5.0,

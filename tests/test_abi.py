@@ -57,8 +57,10 @@ def test_host_validation_without_gpu(abi):
     assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -1
     assert "n_base" in abi.last_error()
     d.n_base = 64
-    d.field = 1
-    assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -2      # Method A: unsupported
+    d.field, d.kind = 1, 1
+    assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -2      # Method A on an octree
+    d.field, d.kind = 5, 0
+    assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -1      # unknown field kind
     d.field = 0
     d.box_size = -1.0
     assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -1

@@ -122,3 +122,28 @@ def test_vertex_box_bounds_and_open_grid_clipping(api, plan):
     with pytest.raises(A.RRError) as e:
         t.build_box((-1, 0, 0), (4, 4, 4))
     assert e.value.status == -6
+
+
+@pytest.mark.parametrize("lo", [(0, 0, 0), (64, 2, 5), (-3, 7, 9)])
+def test_large_box_and_whole_grid_streaming_builds(api, oracle, lo):
+    """n = 128 FP32: the whole-grid build (the streaming configuration, 64x8x64
+    columns) matches the oracle, and boxes above 1/8 of the grid (the same
+    configuration) -- with even, odd and wrapping origins -- equal it on their
+    vertices and leave the others alone."""
+    n, box = 128, 128.0
+    rng = np.random.default_rng(13)
+    phi = rng.standard_normal((n, n, n)).astype(np.float32)
+    g = gpu_grid(api, phi, box)
+    whole = api.TidalTensor(g, "fp32").build().to_torch().cpu().numpy().reshape(n, n, n, 6)
+    ref = oracle.vertex_tensor(phi.astype(np.float64)).reshape(n, n, n, 6)
+    np.testing.assert_allclose(whole, ref, rtol=0, atol=2e-6 * np.abs(ref).max())
+    size = (128, 100, 40)
+    assert 8 * np.prod(size) > n ** 3
+    poison = gpu_grid(api, (1e3 * rng.standard_normal((n, n, n))).astype(np.float32), box)
+    t = api.TidalTensor(poison, "fp32").build()
+    before = t.to_torch().cpu().numpy().reshape(n, n, n, 6)
+    t.build_box(lo, size, grid=g)
+    got = t.to_torch().cpu().numpy().reshape(n, n, n, 6)
+    m = _box_mask(n, lo, size)
+    assert np.array_equal(got[m], whole[m])
+    assert np.array_equal(got[~m], before[~m])
