@@ -298,51 +298,40 @@ __device__ __forceinline__ int slab_child(double o, double r, int m, int l, doub
   return r > 0.0 ? (chi > tm) : (chi <= tm);
 }
 
-// Project corners [c0, c0 + nc) of the leaf's corner block (8 corners x 6
-// components, 24 R each) on P.
-template <typename R, int c0, int nc>
-__device__ __forceinline__ void project_corners(const R* __restrict__ p, const R* P, R* q) {
-  R t[6 * nc];
+// One corner of a leaf's block (8 corners x 6 components) projected on P.
+template <typename R>
+__device__ __forceinline__ R leaf_corner(const R* __restrict__ cv, int64_t cell, int corner,
+                                         const R* P) {
+  const R* p = cv + 48 * cell + 6 * corner;
+  R t[6];
   if constexpr (sizeof(R) == 4) {
-    const float4* p4 = reinterpret_cast<const float4*>(p + 6 * c0);
-#pragma unroll
-    for (int i = 0; i < 6 * nc / 4; ++i) {
-      const float4 x = p4[i];
-      t[4 * i] = x.x; t[4 * i + 1] = x.y; t[4 * i + 2] = x.z; t[4 * i + 3] = x.w;
-    }
+    const float2* p2 = reinterpret_cast<const float2*>(p);
+    const float2 x = p2[0], y = p2[1], z = p2[2];
+    t[0] = x.x; t[1] = x.y; t[2] = y.x; t[3] = y.y; t[4] = z.x; t[5] = z.y;
   } else {
-    const double2* p2 = reinterpret_cast<const double2*>(p + 6 * c0);
-#pragma unroll
-    for (int i = 0; i < 3 * nc; ++i) {
-      const double2 x = p2[i];
-      t[2 * i] = x.x; t[2 * i + 1] = x.y;
-    }
+    const double2* p2 = reinterpret_cast<const double2*>(p);
+    const double2 x = p2[0], y = p2[1], z = p2[2];
+    t[0] = x.x; t[1] = x.y; t[2] = y.x; t[3] = y.y; t[4] = z.x; t[5] = z.y;
   }
+  R acc = P[0] * t[0];
 #pragma unroll
-  for (int v = 0; v < nc; ++v) {
-    R acc = P[0] * t[6 * v];
-#pragma unroll
-    for (int c = 1; c < 6; ++c) acc = fma(P[c], t[6 * v + c], acc);
-    q[c0 + v] = acc;
-  }
+  for (int c = 1; c < 6; ++c) acc = fma(P[c], t[c], acc);
+  return acc;
 }
 
-// The whole block in one go (all loads in flight): the per-crossing load.
+// All eight corners of a leaf in the ray's frame: slot c (bit a: 0 = the
+// face the ray enters through along axis a, 1 = the face it leaves through)
+// is block corner c ^ flip, flip bit a set where n_a > 0 (the ray enters
+// through the upper face).  In two halves, at most four records in flight:
+// this runs at the start of a ray, at level changes and edge crossings only.
 template <typename R>
-__device__ __forceinline__ void load_block(const R* __restrict__ cv, int64_t cell, const R* P,
-                                           R* q) {
-  project_corners<R, 0, 8>(cv + 48 * cell, P, q);
-}
-
-// The block in two halves, the second issued after the first is projected:
-// for the start of a ray, where the ray's set-up state is live as well.
-template <typename R>
-__device__ __forceinline__ void load_block_halves(const R* __restrict__ cv, int64_t cell,
-                                                  const R* P, R* q) {
-  const R* p = cv + 48 * cell;
-  project_corners<R, 0, 4>(p, P, q);
-  asm volatile("" : "+v"(p) : "v"(q[3]));
-  project_corners<R, 4, 4>(p, P, q);
+__device__ __forceinline__ void load_leaf(const R* __restrict__ cv, int64_t cell, int flip,
+                                          const R* P, R* q) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) q[c] = leaf_corner<R>(cv, cell, c ^ flip, P);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int c = 4; c < 8; ++c) q[c] = leaf_corner<R>(cv, cell, c ^ flip, P);
 }
 
 // Cell at level l and coordinates I below base cell `b`; if the tree stops
@@ -364,16 +353,18 @@ __device__ __forceinline__ int descend_from(const Tree& T, int64_t b, int l, con
   return l;
 }
 
-// One ray through the octree.  Per axis the lane keeps, in FP64, the
-// crossing parameter of the current leaf's exit plane, and the level-l
-// coordinates m; the leaf's local coordinate is u = A + S (chi - t_exit)
-// with S = n_a 2^l and A = 0 (n_a > 0, leaving through the lower face) or 1
-// (leaving through the upper face), so it is exact on the exit face.  The
-// wrapped base cell is tracked incrementally (no division per crossing).
-// The next leaf's corner block is loaded together with its child link: a
-// crossing that stays on level 0 or inside the parent oct needs no walk from
-// the base cell, and a refined target (the load is then discarded) or a
-// coarser one is walked.
+// One ray through the octree, in the ray's frame (as the uniform march):
+// per axis the lane keeps, in FP64, the crossing parameter of the current
+// leaf's exit plane and the level-l coordinates m, and the local coordinate
+// f = 1 - |n_a| 2^l (chi - t_exit) runs from 0 on the entry face to exactly 1
+// on the exit face.  The wrapped base cell is tracked incrementally (no
+// division per crossing).  Crossing one face into a leaf of the same level
+// keeps the four projected corner values of that face (same-level leaves
+// share their face corners bit for bit: a vertex's value is computed from
+// the vertex alone) and loads the new leaf's four exit-face corners together
+// with its child link; level changes and edge crossings reload all eight.
+// A crossing that stays on level 0 or inside the parent oct needs no walk
+// from the base cell.
 template <typename R, bool kDebug, bool kNgp>
 __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceArgs& a,
                           const DevBundle& B, int64_t ray) {
@@ -384,6 +375,8 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   R P[6];
   double r[3];
   int m[3], wb[3];
+  R absd[3];
+  int flip = 0;   // block corner of ray-frame slot c: c ^ flip
   {
     const double d[3] = {B.dir[3 * ray + 0], B.dir[3 * ray + 1], B.dir[3 * ray + 2]};
     const double nrm2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -401,6 +394,8 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       m[k] = start_slab(a.o[k], d[k], r[k], chiA, 1.0);
       const int q = m[k] % n;
       wb[k] = q < 0 ? q + n : q;
+      absd[k] = d[k] != 0.0 ? (R)fabs(d[k]) : (R)1e-30;
+      flip |= (d[k] > 0.0) << k;
     }
   }
   int64_t blin = ((int64_t)wb[2] * n + wb[1]) * n + wb[0];
@@ -421,29 +416,28 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     }
   }
   double te[3];
-  R S[3], A[3];
-  // exit parameters and local-coordinate maps of every axis at level l
-  // (S = n_a 2^l is carried from level to level by exact power-of-two scaling)
+  // exit parameters and slopes of every axis at level l (the slope |n_a| 2^l
+  // is carried from level to level by exact power-of-two scaling); an axis
+  // the ray never crosses gets the slope 1e-30 and an exit parameter
+  // (1 - f) 1e30 below any chi, which reproduces its fixed coordinate
   auto set_level = [&](int dl) {
     const double hl = ldexp(1.0, -l);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      S[k] = ldexp(S[k], dl);
       if (r[k] != 0.0) {
+        absd[k] = ldexp(absd[k], dl);
         te[k] = tplane((double)(r[k] > 0.0 ? m[k] : m[k] + 1) * hl, a.o[k], r[k]);
-        A[k] = r[k] > 0.0 ? (R)0 : (R)1;
       } else {
-        // never crossed: slope 0 and a finite exit parameter below any chi
-        te[k] = -1e30;
-        A[k] = (R)ldexp(a.o[k] - (double)m[k] * hl, l);
+        te[k] = -(1.0 - ldexp(a.o[k] - (double)m[k] * hl, l)) * 1e30;
       }
     }
   };
-#pragma unroll
-  for (int k = 0; k < 3; ++k) S[k] = (R)B.dir[3 * ray + k];
   set_level(l);
+  R fA[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
   R q[8];
-  if constexpr (!kNgp) load_block_halves<R>(cv, cell, P, q);
+  if constexpr (!kNgp) load_leaf<R>(cv, cell, flip, P, q);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
@@ -475,6 +469,9 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
 
     const R L = (R)(chiA - chiB);
     R ic;
+    R fB[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) fB[k] = (R)1 - absd[k] * (R)(chiB - te[k]);
     if constexpr (kNgp) {
       // Eq. (Iclensing_ngp): the leaf's centre value times the integral of g,
       // L (g(mid) - L^2 / (12 chi_s)) with g(chi) = chi (chi_s - chi) / chi_s
@@ -486,13 +483,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       const R gm = (R)mid * (R)(B.chi_s - mid) - L * L * (R)(1.0 / 12.0);
       ic = Qc * (gm * L * inv_chis) * scale;
     } else {
-      R uA[3], uB[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        uA[k] = fma(S[k], (R)(chiA - te[k]), A[k]);
-        uB[k] = fma(S[k], (R)(chiB - te[k]), A[k]);
-      }
-      ic = cell_integral<R>(q, uA, uB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+      ic = cell_integral<R>(q, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
     }
     if constexpr (sizeof(R) == 4) {
       kahan_add(sum, comp, ic);
@@ -542,30 +533,60 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     } else {
       lev = descend_from(T, blin, l, m, nc);
     }
-    // load the target's corner block together with its child link; a refined
-    // target (rare) drops the block and descends to the child next to the
-    // crossed face(s), slab rule on the other axes
+    // the target: a same-level leaf across one face keeps four corner values
+    // and loads the other four together with its child link; a refined target
+    // (the loads are dropped), a coarser one or an edge crossing reloads all
     const int l_in = l;
-    for (;;) {
-      const int kc = T.child[nc];
-      if constexpr (!kNgp) load_block<R>(cv, nc, P, q);
-      if (kc < 0) break;
-      int ch = 0;
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const int bit = stepped[ax] ? (r[ax] > 0.0 ? 1 : 0)
-                                    : slab_child(a.o[ax], r[ax], m[ax], l, chiA);
-        m[ax] = 2 * m[ax] + bit;
-        ch |= bit << ax;
+    const bool single = (int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1;
+    int kc = T.child[nc];
+    bool kept = false;
+    if constexpr (!kNgp) {
+      if (lev == l && single) {
+        const bool k0 = stepped[0], k1 = stepped[1];
+        // slots of the new exit face: (1 << k) | i_a << a | i_b << b, a < b the other axes
+        const int sk = k0 ? 1 : (k1 ? 2 : 4);
+        const int sa = k0 ? 2 : 1;
+        const int sb = k0 || k1 ? 4 : 2;
+        const R F0 = leaf_corner<R>(cv, nc, sk ^ flip, P);
+        const R F1 = leaf_corner<R>(cv, nc, (sk | sa) ^ flip, P);
+        const R F2 = leaf_corner<R>(cv, nc, (sk | sb) ^ flip, P);
+        const R F3 = leaf_corner<R>(cv, nc, (sk | sa | sb) ^ flip, P);
+        if (kc < 0) {
+          const R n0 = k0 ? q[1] : (k1 ? q[2] : q[4]);
+          const R n1 = k0 ? F0 : (k1 ? q[3] : q[5]);
+          const R n2 = k0 ? q[3] : (k1 ? F0 : q[6]);
+          const R n3 = k0 || k1 ? F1 : q[7];
+          const R n4 = k0 ? q[5] : (k1 ? q[6] : F0);
+          const R n5 = k0 ? F2 : (k1 ? q[7] : F1);
+          const R n6 = k0 ? q[7] : F2;
+          q[0] = n0; q[1] = n1; q[2] = n2; q[3] = n3;
+          q[4] = n4; q[5] = n5; q[6] = n6; q[7] = F3;
+          kept = true;
+        }
       }
-      nc = T.nb + 8 * (int64_t)kc + ch;
-      ++l;
     }
-    if (lev < l_in) {
-      // coarser neighbour
+    if (!kept) {
+      // refined target: the child next to the crossed face(s), slab rule elsewhere
+      while (kc >= 0) {
+        int ch = 0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) m[k] >>= (l_in - lev);
-      l = lev;
+        for (int ax = 0; ax < 3; ++ax) {
+          const int bit = stepped[ax] ? (r[ax] > 0.0 ? 1 : 0)
+                                      : slab_child(a.o[ax], r[ax], m[ax], l, chiA);
+          m[ax] = 2 * m[ax] + bit;
+          ch |= bit << ax;
+        }
+        nc = T.nb + 8 * (int64_t)kc + ch;
+        ++l;
+        kc = T.child[nc];
+      }
+      if (lev < l_in) {
+        // coarser neighbour
+#pragma unroll
+        for (int k = 0; k < 3; ++k) m[k] >>= (l_in - lev);
+        l = lev;
+      }
+      if constexpr (!kNgp) load_leaf<R>(cv, nc, flip, P, q);
     }
     if (l != l_in) {
       set_level(l - l_in);
@@ -576,6 +597,11 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         if (stepped[k])
           te[k] = tplane((double)(r[k] > 0.0 ? m[k] : m[k] + 1) * hl, a.o[k], r[k]);
     }
+    // the entry point: on the crossed faces exactly 0, elsewhere the exit
+    // coordinate of the last leaf (same level) or recomputed at the new level
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      fA[k] = stepped[k] ? (R)0 : (l != l_in ? (R)1 - absd[k] * (R)(chiA - te[k]) : fB[k]);
     cell = nc;
   }
   if (!(sum == sum) || sum - sum != (R)0) st = RR_RAY_NONFINITE;
