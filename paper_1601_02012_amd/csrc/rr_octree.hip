@@ -299,10 +299,12 @@ __device__ __forceinline__ int slab_child(double o, double r, int m, int l, doub
 }
 
 // One corner of a leaf's block (8 corners x 6 components) projected on P.
-template <typename R>
-__device__ __forceinline__ R leaf_corner(const R* __restrict__ cv, int64_t cell, int corner,
+template <typename R, typename Off>
+__device__ __forceinline__ R leaf_corner(const R* __restrict__ cv, Off cell, int corner,
                                          const R* P) {
-  const R* p = cv + 48 * cell + 6 * corner;
+  // byte offset in Off (32 bit when the whole block array is below 4 GiB)
+  const Off off = cell * (Off)(48 * sizeof(R)) + (Off)(corner * 6 * (int)sizeof(R));
+  const R* p = reinterpret_cast<const R*>(reinterpret_cast<const char*>(cv) + (uint64_t)off);
   R t[6];
   if constexpr (sizeof(R) == 4) {
     const float2* p2 = reinterpret_cast<const float2*>(p);
@@ -324,21 +326,21 @@ __device__ __forceinline__ R leaf_corner(const R* __restrict__ cv, int64_t cell,
 // is block corner c ^ flip, flip bit a set where n_a > 0 (the ray enters
 // through the upper face).  In two halves, at most four records in flight:
 // this runs at the start of a ray, at level changes and edge crossings only.
-template <typename R>
-__device__ __forceinline__ void load_leaf(const R* __restrict__ cv, int64_t cell, int flip,
+template <typename R, typename Off>
+__device__ __forceinline__ void load_leaf(const R* __restrict__ cv, Off cell, int flip,
                                           const R* P, R* q) {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) q[c] = leaf_corner<R>(cv, cell, c ^ flip, P);
+  for (int c = 0; c < 4; ++c) q[c] = leaf_corner<R, Off>(cv, cell, c ^ flip, P);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int c = 4; c < 8; ++c) q[c] = leaf_corner<R>(cv, cell, c ^ flip, P);
+  for (int c = 4; c < 8; ++c) q[c] = leaf_corner<R, Off>(cv, cell, c ^ flip, P);
 }
 
 // Cell at level l and coordinates I below base cell `b`; if the tree stops
 // above l, the covering leaf.  Returns the level of the cell found.
-__device__ __forceinline__ int descend_from(const Tree& T, int64_t b, int l, const int* I,
-                                            int64_t& cell) {
-  int64_t c = b;
+template <typename Off>
+__device__ __forceinline__ int descend_from(const Tree& T, Off b, int l, const int* I, Off& cell) {
+  Off c = b;
   for (int lev = 1; lev <= l; ++lev) {
     const int k = T.child[c];
     if (k < 0) {
@@ -347,7 +349,7 @@ __device__ __forceinline__ int descend_from(const Tree& T, int64_t b, int l, con
     }
     const int s = l - lev;
     const int ch = ((I[0] >> s) & 1) | (((I[1] >> s) & 1) << 1) | (((I[2] >> s) & 1) << 2);
-    c = T.nb + 8 * (int64_t)k + ch;
+    c = (Off)T.nb + 8 * (Off)k + (Off)ch;
   }
   cell = c;
   return l;
@@ -365,7 +367,7 @@ __device__ __forceinline__ int descend_from(const Tree& T, int64_t b, int l, con
 // with its child link; level changes and edge crossings reload all eight.
 // A crossing that stays on level 0 or inside the parent oct needs no walk
 // from the base cell.
-template <typename R, bool kDebug, bool kNgp>
+template <typename R, bool kDebug, bool kNgp, typename Off>
 __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceArgs& a,
                           const DevBundle& B, int64_t ray) {
   const int64_t out = B.ray_offset + ray;
@@ -398,9 +400,9 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       flip |= (d[k] > 0.0) << k;
     }
   }
-  int64_t blin = ((int64_t)wb[2] * n + wb[1]) * n + wb[0];
+  Off blin = ((Off)wb[2] * (Off)n + (Off)wb[1]) * (Off)n + (Off)wb[0];
   int l = 0;
-  int64_t cell = blin;
+  Off cell = blin;
   {
     int k;
     while ((k = T.child[cell]) >= 0) {
@@ -411,7 +413,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         m[ax] = 2 * m[ax] + bit;
         ch |= bit << ax;
       }
-      cell = T.nb + 8 * (int64_t)k + ch;
+      cell = (Off)T.nb + 8 * (Off)k + (Off)ch;
       ++l;
     }
   }
@@ -437,7 +439,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
 #pragma unroll
   for (int k = 0; k < 3; ++k) fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
   R q[8];
-  if constexpr (!kNgp) load_leaf<R>(cv, cell, flip, P, q);
+  if constexpr (!kNgp) load_leaf<R, Off>(cv, cell, flip, P, q);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
@@ -475,7 +477,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     if constexpr (kNgp) {
       // Eq. (Iclensing_ngp): the leaf's centre value times the integral of g,
       // L (g(mid) - L^2 / (12 chi_s)) with g(chi) = chi (chi_s - chi) / chi_s
-      const R* tc = cv + 6 * cell;
+      const R* tc = cv + 6 * (uint64_t)cell;
       R Qc = P[0] * tc[0];
 #pragma unroll
       for (int c = 1; c < 6; ++c) Qc = fma(P[c], tc[c], Qc);
@@ -491,10 +493,10 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       sum += ic;
     }
     if constexpr (kDebug) {
-      if (a.hash) hv = fnv_piece(hv, cell, chiA, chiB);
+      if (a.hash) hv = fnv_piece(hv, (int64_t)cell, chiA, chiB);
       if (a.log && count < a.log_stride) {
         LogRecord* L0 = reinterpret_cast<LogRecord*>(a.log) + out * a.log_stride + count;
-        L0->cell = cell;
+        L0->cell = (int64_t)cell;
         L0->chi_a = chiA;
         L0->chi_b = chiB;
       }
@@ -521,17 +523,17 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         }
       }
     }
-    if (moved) blin = ((int64_t)wb[2] * n + wb[1]) * n + wb[0];
+    if (moved) blin = ((Off)wb[2] * (Off)n + (Off)wb[1]) * (Off)n + (Off)wb[0];
     // the level-l cell past the face: a base cell, a sibling, or a walk
-    int64_t nc;
+    Off nc;
     int lev = l;
     if (l == 0) {
       nc = blin;
     } else if (sib) {
       const int ch = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
-      nc = cell + (ch - ch_old);
+      nc = cell + (Off)(ch - ch_old);
     } else {
-      lev = descend_from(T, blin, l, m, nc);
+      lev = descend_from<Off>(T, blin, l, m, nc);
     }
     // the target: a same-level leaf across one face keeps four corner values
     // and loads the other four together with its child link; a refined target
@@ -547,10 +549,10 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         const int sk = k0 ? 1 : (k1 ? 2 : 4);
         const int sa = k0 ? 2 : 1;
         const int sb = k0 || k1 ? 4 : 2;
-        const R F0 = leaf_corner<R>(cv, nc, sk ^ flip, P);
-        const R F1 = leaf_corner<R>(cv, nc, (sk | sa) ^ flip, P);
-        const R F2 = leaf_corner<R>(cv, nc, (sk | sb) ^ flip, P);
-        const R F3 = leaf_corner<R>(cv, nc, (sk | sa | sb) ^ flip, P);
+        const R F0 = leaf_corner<R, Off>(cv, nc, sk ^ flip, P);
+        const R F1 = leaf_corner<R, Off>(cv, nc, (sk | sa) ^ flip, P);
+        const R F2 = leaf_corner<R, Off>(cv, nc, (sk | sb) ^ flip, P);
+        const R F3 = leaf_corner<R, Off>(cv, nc, (sk | sa | sb) ^ flip, P);
         if (kc < 0) {
           const R n0 = k0 ? q[1] : (k1 ? q[2] : q[4]);
           const R n1 = k0 ? F0 : (k1 ? q[3] : q[5]);
@@ -576,7 +578,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
           m[ax] = 2 * m[ax] + bit;
           ch |= bit << ax;
         }
-        nc = T.nb + 8 * (int64_t)kc + ch;
+        nc = (Off)T.nb + 8 * (Off)kc + (Off)ch;
         ++l;
         kc = T.child[nc];
       }
@@ -586,7 +588,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         for (int k = 0; k < 3; ++k) m[k] >>= (l_in - lev);
         l = lev;
       }
-      if constexpr (!kNgp) load_leaf<R>(cv, nc, flip, P, q);
+      if constexpr (!kNgp) load_leaf<R, Off>(cv, nc, flip, P, q);
     }
     if (l != l_in) {
       set_level(l - l_in);
@@ -618,7 +620,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   }
 }
 
-template <typename R, bool kDebug, bool kNgp>
+template <typename R, bool kDebug, bool kNgp, typename Off>
 __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -626,10 +628,10 @@ __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const Trace
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kNgp>(T, cv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kNgp, Off>(T, cv, a, B, (int64_t)iy * B.nx + ix);
 }
 
-template <typename R, bool kDebug, bool kNgp>
+template <typename R, bool kDebug, bool kNgp, typename Off>
 __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __restrict__ cv,
                                                            TraceArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -639,12 +641,12 @@ __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __re
   const int64_t tile =
       ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
-  oct_tile<R, kDebug, kNgp>(T, cv, a, tile, lane);
+  oct_tile<R, kDebug, kNgp, Off>(T, cv, a, tile, lane);
 }
 
-template <typename R, bool kDebug, bool kNgp>
-__global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* __restrict__ cv,
-                                                               TraceArgs a) {
+// FP32: four waves per SIMD (at most 128 VGPRs) fit without spills
+template <typename R, bool kDebug, bool kNgp, typename Off>
+__global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* __restrict__ cv, TraceArgs a) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     unsigned long long t = 0;
@@ -653,22 +655,22 @@ __global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* 
     const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
     if (tile >= a.n_tiles) break;
-    oct_tile<R, kDebug, kNgp>(T, cv, a, tile, lane);
+    oct_tile<R, kDebug, kNgp, Off>(T, cv, a, tile, lane);
   }
 }
 
-template <typename R, bool kDebug, bool kNgp>
+template <typename R, bool kDebug, bool kNgp, typename Off>
 hipError_t launch_march(const Tree& T, const void* cv, const TraceArgs& a, int persistent,
                         int grid_waves, hipStream_t s) {
   if (persistent) {
     const int blocks = (grid_waves + 3) / 4;
-    hipLaunchKernelGGL((march_octree_persistent<R, kDebug, kNgp>), dim3(blocks), dim3(256), 0, s, T,
+    hipLaunchKernelGGL((march_octree_persistent<R, kDebug, kNgp, Off>), dim3(blocks), dim3(256), 0, s, T,
                        (const R*)cv, a);
   } else {
     int64_t blocks = (a.n_tiles + 3) / 4;
     if (blocks == 0) return hipSuccess;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL((march_octree_kernel<R, kDebug, kNgp>), dim3((unsigned)blocks), dim3(256), 0, s,
+    hipLaunchKernelGGL((march_octree_kernel<R, kDebug, kNgp, Off>), dim3((unsigned)blocks), dim3(256), 0, s,
                        T, (const R*)cv, a);
   }
   return hipGetLastError();
@@ -709,23 +711,35 @@ hipError_t OctreeTensor::build(const void* values, int dtype, hipStream_t s) {
                          : build_all<double, double>(*this, values, s);
 }
 
+namespace {
+
+template <typename R, bool kNgp>
+hipError_t launch_march_w(const Tree& T, const void* cv, int64_t n_cells, const TraceArgs& a,
+                          int persistent, int grid_waves, hipStream_t s) {
+  const bool dbg = a.hash || a.log || a.count;
+  // 32-bit cell indices and byte offsets when the corner blocks are below 4 GiB
+  const bool small = n_cells * 48 * (int64_t)sizeof(R) < (1ll << 32);
+  if (small)
+    return dbg ? launch_march<R, true, kNgp, uint32_t>(T, cv, a, persistent, grid_waves, s)
+               : launch_march<R, false, kNgp, uint32_t>(T, cv, a, persistent, grid_waves, s);
+  return dbg ? launch_march<R, true, kNgp, uint64_t>(T, cv, a, persistent, grid_waves, s)
+             : launch_march<R, false, kNgp, uint64_t>(T, cv, a, persistent, grid_waves, s);
+}
+
+}  // namespace
+
 hipError_t OctreeTensor::march(const TraceArgs& a, int persistent, int grid_waves,
                                hipStream_t s) {
   if (a.n_tiles == 0) return hipSuccess;
   Tree T{child_oct_dev, reinterpret_cast<const int4*>(oct_info), n, (int64_t)n * n * n};
-  const bool dbg = a.hash || a.log || a.count;
   if (a.mode == 1) {   // NGP: cell-centre records, 6 per cell
     if (precision == RR_PREC_FP32_KAHAN)
-      return dbg ? launch_march<float, true, true>(T, centre, a, persistent, grid_waves, s)
-                 : launch_march<float, false, true>(T, centre, a, persistent, grid_waves, s);
-    return dbg ? launch_march<double, true, true>(T, centre, a, persistent, grid_waves, s)
-               : launch_march<double, false, true>(T, centre, a, persistent, grid_waves, s);
+      return launch_march_w<float, true>(T, centre, n_cells, a, persistent, grid_waves, s);
+    return launch_march_w<double, true>(T, centre, n_cells, a, persistent, grid_waves, s);
   }
   if (precision == RR_PREC_FP32_KAHAN)
-    return dbg ? launch_march<float, true, false>(T, corners, a, persistent, grid_waves, s)
-               : launch_march<float, false, false>(T, corners, a, persistent, grid_waves, s);
-  return dbg ? launch_march<double, true, false>(T, corners, a, persistent, grid_waves, s)
-             : launch_march<double, false, false>(T, corners, a, persistent, grid_waves, s);
+    return launch_march_w<float, false>(T, corners, n_cells, a, persistent, grid_waves, s);
+  return launch_march_w<double, false>(T, corners, n_cells, a, persistent, grid_waves, s);
 }
 
 }  // namespace rr
