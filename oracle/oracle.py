@@ -18,7 +18,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle_rro.so")
-SOURCES = ["rro_uniform.c", "rro_adjoint.c", "rro_octree.c", "rro_method_a.c"]
+SOURCES = ["rro_uniform.c", "rro_adjoint.c", "rro_octree.c", "rro_method_a.c",
+           "rro_sources.c"]
 
 RAY_OK, RAY_OUT_OF_DOMAIN, RAY_MAX_STEPS = 0, 1, 2
 Q_KAPPA, Q_GAMMA1, Q_GAMMA2 = 0, 1, 2
@@ -84,6 +85,14 @@ def lib():
         L.rro_trace_uniform_method_a.argtypes = [i32, i32, dbl, vp, i64, vp, vp, vp, vp, dbl, dbl,
                                                  vp, i64, i32, vp, vp, vp, vp]
         L.rro_trace_uniform_method_a.restype = i32
+        L.rro_trace_uniform_sources.argtypes = [i32, i32, dbl, vp, i64, vp, vp, vp, i32, vp,
+                                                dbl, i32, vp, i64, i32, vp, vp, vp, vp, vp]
+        L.rro_trace_uniform_sources.restype = i32
+        L.rro_trace_octree_sources.argtypes = [vp, dbl, vp, i64, vp, vp, vp, i32, vp, dbl, i32,
+                                               vp, i64, i32, vp, vp, vp, vp, vp]
+        L.rro_trace_octree_sources.restype = i32
+        L.rro_kappa_from_pieces.argtypes = [i64, i32, vp, dbl, i32, vp, vp, vp]
+        L.rro_cell_moments.argtypes = [vp, vp, dbl, vp, vp, dbl, dbl, vp]
         L.rro_projection.argtypes = [vp, vp, i32]
         L.rro_projection.restype = dbl
         _lib = L
@@ -201,6 +210,64 @@ def cell_integral_k(Q, p1, h, direction, o, chis, chiA, chiB):
                                      _p(_f64(o)), float(chis), float(chiA), float(chiB))
 
 
+@dataclass
+class SourcesResult:
+    moments: np.ndarray      # (n_rays, 2): int chi Q, int chi^2 Q left after the last stop
+    pieces: np.ndarray       # (n_rays, n_src, 2): handed out at each source
+    hash: np.ndarray
+    ncross: np.ndarray
+    status: np.ndarray
+
+
+def _sources_io(nr, n_src, chi_src, moments, pieces):
+    src = _f64(chi_src).reshape(-1)
+    assert src.shape[0] == n_src
+    mom = np.zeros((nr, 2)) if moments is None else np.array(moments, dtype=np.float64)
+    pcs = np.zeros((nr, n_src, 2)) if pieces is None else np.array(pieces, dtype=np.float64)
+    return src, np.ascontiguousarray(mom), np.ascontiguousarray(pcs)
+
+
+def trace_uniform_sources(n, box, observer, dirs, chi_hi, chi_lo, chi_src, *, tv=None, phi=None,
+                          open_boundary=False, kappa_scale=1.0, quantity=Q_KAPPA,
+                          moments=None, pieces=None, max_steps=1 << 40,
+                          threads=0) -> SourcesResult:
+    """One walk for many source distances (Eqs. Isources, Isources1), FP64.
+    ``moments`` / ``pieces`` carry the state of earlier chi windows."""
+    dirs = _f64(dirs).reshape(-1, 3)
+    nr = dirs.shape[0]
+    if tv is None:
+        tv = vertex_tensor(phi, open_boundary)
+    src, mom, pcs = _sources_io(nr, len(np.atleast_1d(chi_src)), chi_src, moments, pieces)
+    hsh = np.zeros(nr, dtype=np.uint64)
+    ncr = np.zeros(nr, dtype=np.int64)
+    st = np.zeros(nr, dtype=np.int32)
+    lib().rro_trace_uniform_sources(n, int(open_boundary), float(box), _p(_f64(observer)), nr,
+                                    _p(dirs), _p(_per_ray(chi_hi, nr)), _p(_per_ray(chi_lo, nr)),
+                                    src.shape[0], _p(src), float(kappa_scale), int(quantity),
+                                    _p(_f64(tv)), int(max_steps), int(threads), _p(mom), _p(pcs),
+                                    _p(hsh), _p(ncr), _p(st))
+    return SourcesResult(mom, pcs, hsh, ncr, st)
+
+
+def cell_moments(Q, p1, h, direction, o, chi_a, chi_b):
+    """(int chi Q, int chi^2 Q) over one cell's piece [chi_b, chi_a] (grid units)."""
+    out = np.zeros(2)
+    lib().rro_cell_moments(_p(_f64(Q)), _p(_f64(p1)), float(h), _p(_f64(direction)),
+                           _p(_f64(o)), float(chi_a), float(chi_b), _p(out))
+    return out
+
+
+def kappa_from_pieces(chi_src, box, n_base, moments, pieces):
+    """kappa (n_rays, n_src) of every source after the walk reached the observer."""
+    src = _f64(chi_src).reshape(-1)
+    mom = _f64(moments).reshape(-1, 2)
+    pcs = _f64(pieces).reshape(mom.shape[0], src.shape[0], 2)
+    out = np.zeros((mom.shape[0], src.shape[0]))
+    lib().rro_kappa_from_pieces(mom.shape[0], src.shape[0], _p(src), float(box), int(n_base),
+                                _p(mom), _p(pcs), _p(out))
+    return out
+
+
 def trace_adjoint_uniform(n, box, observer, dirs, chi_s, chi_hi, chi_lo, dl_dkappa,
                           kappa_scale=1.0, threads=0):
     dirs = _f64(dirs).reshape(-1, 3)
@@ -307,3 +374,24 @@ def trace_octree(t: Octree, box, observer, dirs, chi_s, chi_hi, chi_lo, *, cv=No
                            _p(ncr), _p(st),
                            _p(log), int(log_stride))
     return TraceResult(kappa, hsh, ncr, st, log)
+
+
+def trace_octree_sources(t: Octree, box, observer, dirs, chi_hi, chi_lo, chi_src, *, cv=None,
+                         phi=None, kappa_scale=1.0, quantity=Q_KAPPA, moments=None, pieces=None,
+                         max_steps=1 << 40, threads=0) -> SourcesResult:
+    """The many-source walk through the octree (FP64); ``cv`` per-leaf corner
+    tensors, or ``phi`` to compute them here."""
+    dirs = _f64(dirs).reshape(-1, 3)
+    nr = dirs.shape[0]
+    if cv is None:
+        cv = corner_tensor_octree(t, centre_tensor_octree(t, phi))
+    src, mom, pcs = _sources_io(nr, len(np.atleast_1d(chi_src)), chi_src, moments, pieces)
+    hsh = np.zeros(nr, dtype=np.uint64)
+    ncr = np.zeros(nr, dtype=np.int64)
+    st = np.zeros(nr, dtype=np.int32)
+    lib().rro_trace_octree_sources(t.ref(), float(box), _p(_f64(observer)), nr, _p(dirs),
+                                   _p(_per_ray(chi_hi, nr)), _p(_per_ray(chi_lo, nr)),
+                                   src.shape[0], _p(src), float(kappa_scale), int(quantity),
+                                   _p(_f64(cv)), int(max_steps), int(threads), _p(mom), _p(pcs),
+                                   _p(hsh), _p(ncr), _p(st))
+    return SourcesResult(mom, pcs, hsh, ncr, st)

@@ -18,6 +18,7 @@
  *   d_N coefficients         App. B, Eq. (dns)
  *   per-cell lensing integral Eq. (Iclensing); NGP variant Eq. (Iclensing_ngp)
  *   kappa integrand          Eqs. (n1n1), (n2n2); shear Eqs. (gamma1), (gamma2), (n1n2)
+ *   many source distances    Sec. VII, Eqs. (Isources), (Isources1)
  *
  * Units: lengths are converted to base-grid units, h0 = L / n_base,
  * o~ = o / h0, chi~ = chi / h0; a level-l cell has size 2^-l.  kappa is
@@ -92,6 +93,31 @@ int32_t rro_trace_uniform_method_a(int32_t n, int32_t open, double box, const do
 double rro_cell_integral_k(const double* Q, const double* p1, double h, const double* dir,
                            const double* o, double chis, double chiA, double chiB);
 
+/* Many source distances in one walk (Sec. VII, Eqs. Isources, Isources1).
+ * chi_src: n_src source distances (box units), strictly decreasing.  Per ray
+ * the walk integrates kappa_scale * int chi Q and kappa_scale * int chi^2 Q
+ * (grid units) into moments[2 r + 0..1] (in/out), stops at every chi_src[j]
+ * with chi_lo <= chi_src[j] < chi_hi (a cell holding it is cut into two
+ * pieces, each hashed and counted), writes the accumulated pair to
+ * pieces[(r n_src + j) 2 + 0..1] and restarts it from zero.  Other pieces
+ * are left as they are.  quantity as for rro_trace_uniform. */
+int32_t rro_trace_uniform_sources(int32_t n, int32_t open, double box, const double* observer,
+                                  int64_t n_rays, const double* dir, const double* chi_hi,
+                                  const double* chi_lo, int32_t n_src, const double* chi_src,
+                                  double kappa_scale, int32_t quantity, const double* tv,
+                                  int64_t max_steps, int32_t n_threads, double* moments,
+                                  double* pieces, uint64_t* hash, int64_t* ncross,
+                                  int32_t* status);
+/* One cell of the two integrals: out[0] = int chi Q, out[1] = int chi^2 Q
+ * over [chi_B, chi_A] (arguments as rro_cell_integral). */
+void rro_cell_moments(const double* Q, const double* p1, double h, const double* dir,
+                      const double* o, double chiA, double chiB, double* out);
+/* kappa[r n_src + j] of every source once the walk has reached the observer
+ * (moments then hold what lies below the nearest source). */
+void rro_kappa_from_pieces(int64_t n_rays, int32_t n_src, const double* chi_src, double box,
+                           int32_t n_base, const double* moments, const double* pieces,
+                           double* kappa);
+
 /* Adjoint of kappa = A(Phi) for a uniform grid: dL/dPhi += A^T (dL/dkappa).
  * Explicit transpose of: per-cell integral -> vertex average -> FD stencil. */
 int32_t rro_trace_adjoint_uniform(int32_t n, double box, const double* observer,
@@ -142,6 +168,14 @@ int32_t rro_trace_octree(const rro_octree* t, double box, const double* observer
                          int64_t max_steps,
                          int32_t n_threads, double* kappa, uint64_t* hash, int64_t* ncross,
                          int32_t* status, rro_segment* log, int64_t log_stride);
+/* The many-source walk through the octree (per-leaf corner tensors cv). */
+int32_t rro_trace_octree_sources(const rro_octree* t, double box, const double* observer,
+                                 int64_t n_rays, const double* dir, const double* chi_hi,
+                                 const double* chi_lo, int32_t n_src, const double* chi_src,
+                                 double kappa_scale, int32_t quantity, const double* cv,
+                                 int64_t max_steps, int32_t n_threads, double* moments,
+                                 double* pieces, uint64_t* hash, int64_t* ncross,
+                                 int32_t* status);
 
 #ifdef __cplusplus
 }

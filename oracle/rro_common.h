@@ -146,11 +146,12 @@ static inline double rro_quantity(const rro_ray* ray, const double* T) {
   }
 }
 
-/* Eq. (Iclensing): I_c for one cell from the vertex values Q[1..8] of the
- * paper's P_i (i = 1 + ix + 2 iy + 4 iz), lower corner p1, cell size h. */
-static inline double rro_integral_trilinear_q(const rro_ray* ray, const double* Q,
-                                              const double* p1, double h, double chiA,
-                                              double chiB) {
+/* The cubic Q(chi_A + s) = d_1 + d_2 s + d_3 s^2 + d_4 s^3 of the trilinear
+ * field along the ray inside one cell (App. B, Eq. dns), from the vertex
+ * values Q[1..8] of the paper's P_i (i = 1 + ix + 2 iy + 4 iz), lower corner
+ * p1 and cell size h. */
+static inline void rro_dn(const rro_ray* ray, const double* Q, const double* p1, double h,
+                          double chiA, double* d) {
   /* Eq. (trilinear_coef) */
   double al[9];
   al[1] = Q[1];
@@ -168,7 +169,6 @@ static inline double rro_integral_trilinear_q(const rro_ray* ray, const double* 
   const double sx = ray->n[0], sy = ray->n[1], sz = ray->n[2];
   const double h2 = h * h, h3 = h * h * h;
   /* App. B, Eq. (dns) */
-  double d[5];
   d[1] = al[1] + (al[2] * a + al[3] * b + al[4] * c) / h +
          (al[5] * a * b + al[6] * b * c + al[7] * a * c) / h2 + al[8] * a * b * c / h3;
   d[2] = (al[2] * sx + al[3] * sy + al[4] * sz) / h +
@@ -178,6 +178,14 @@ static inline double rro_integral_trilinear_q(const rro_ray* ray, const double* 
   d[3] = (al[5] * sx * sy + al[7] * sx * sz + al[6] * sy * sz) / h2 +
          (al[8] * a * sy * sz + al[8] * b * sx * sz + al[8] * c * sx * sy) / h3;
   d[4] = al[8] / h3 * (sx * sy * sz);
+}
+
+/* Eq. (Iclensing): I_c for one cell from the vertex values Q[1..8]. */
+static inline double rro_integral_trilinear_q(const rro_ray* ray, const double* Q,
+                                              const double* p1, double h, double chiA,
+                                              double chiB) {
+  double d[5];
+  rro_dn(ray, Q, p1, h, chiA, d);
   /* Eq. (Iclensing) with R = chi_B - chi_A */
   const double chis = ray->chis;
   const double R = chiB - chiA;
@@ -189,6 +197,28 @@ static inline double rro_integral_trilinear_q(const rro_ray* ray, const double* 
                    RN * R * R / (N + 2));
   }
   return sum / chis;
+}
+
+/* The two integrals of Eq. (Isources) over one cell, int chi Q dchi and
+ * int chi^2 Q dchi from chi_B to chi_A, from the same cubic: with
+ * chi = chi_A + s and R = chi_B - chi_A,
+ *   int chi Q   = -sum_N d_N (chi_A R^N / N + R^(N+1) / (N+1))
+ *   int chi^2 Q = -sum_N d_N (chi_A^2 R^N / N + 2 chi_A R^(N+1) / (N+1) + R^(N+2) / (N+2)),
+ * so that their combination A - B / chi_s is Eq. (Iclensing). */
+static inline void rro_moments_trilinear_q(const rro_ray* ray, const double* Q, const double* p1,
+                                           double h, double chiA, double chiB, double* ma,
+                                           double* mb) {
+  double d[5];
+  rro_dn(ray, Q, p1, h, chiA, d);
+  const double R = chiB - chiA;
+  double sa = 0.0, sb = 0.0, RN = 1.0;
+  for (int N = 1; N <= 4; ++N) {
+    RN *= R;
+    sa += d[N] * (chiA * RN / N + RN * R / (N + 1));
+    sb += d[N] * (chiA * chiA * RN / N + 2.0 * chiA * RN * R / (N + 1) + RN * R * R / (N + 2));
+  }
+  *ma = -sa;
+  *mb = -sb;
 }
 
 static inline double rro_integral_trilinear(const rro_ray* ray, const double tcorner[8][6],

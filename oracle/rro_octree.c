@@ -427,3 +427,114 @@ int32_t rro_trace_octree(const rro_octree* t, double box, const double* observer
   }
   return 0;
 }
+
+/* The many-source walk (Eqs. Isources, Isources1; see rro_sources.c) through
+ * the octree: the same descent and ascent as rro_trace_octree, with the walk
+ * also stopping at every source distance in [chi_lo, chi_hi). */
+int32_t rro_trace_octree_sources(const rro_octree* t, double box, const double* observer,
+                                 int64_t n_rays, const double* dir, const double* chi_hi,
+                                 const double* chi_lo, int32_t n_src, const double* chi_src,
+                                 double kappa_scale, int32_t quantity, const double* cv,
+                                 int64_t max_steps, int32_t n_threads, double* moments,
+                                 double* pieces, uint64_t* hash, int64_t* ncross,
+                                 int32_t* status) {
+  const double h0 = box / (double)t->n;
+  double o[3];
+  for (int a = 0; a < 3; ++a) o[a] = observer[a] / h0;
+  double* src = (double*)malloc(sizeof(double) * (size_t)(n_src > 0 ? n_src : 1));
+  for (int32_t j = 0; j < n_src; ++j) src[j] = chi_src[j] / h0;
+  if (n_threads > 0) rro_set_threads(n_threads);
+  const int64_t nbase = (int64_t)t->n * t->n * t->n;
+
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < n_rays; ++r) {
+    rro_ray ray;
+    rro_ray_init(&ray, dir + 3 * r, o, 1.0, quantity);
+    const double lo = chi_lo[r] / h0;
+    double chiA = chi_hi[r] / h0;
+    int64_t m[3];
+    for (int a = 0; a < 3; ++a) m[a] = rro_start_slab(&ray, a, chiA, 1.0);
+    loc_t cur = descend(t, 0, m);
+    int32_t l = 0;
+    while (t->child_oct[cur.cell] >= 0) {
+      int child = 0;
+      for (int a = 0; a < 3; ++a) {
+        const int bit = slab_child(&ray, a, m[a], l, chiA);
+        m[a] = 2 * m[a] + bit;
+        child |= bit << a;
+      }
+      cur.cell = nbase + 8 * (int64_t)t->child_oct[cur.cell] + child;
+      ++l;
+    }
+    int32_t jn = 0;
+    while (jn < n_src && !(src[jn] < chiA)) ++jn;
+
+    double A = moments[2 * r + 0], B = moments[2 * r + 1];
+    uint64_t hv = RRO_FNV_OFFSET;
+    int64_t count = 0;
+    int32_t st = RRO_RAY_OK;
+    for (;;) {
+      if (count >= max_steps) {
+        st = RRO_RAY_MAX_STEPS;
+        break;
+      }
+      const double hl = ldexp(1.0, -l);
+      const double stop = (jn < n_src && src[jn] >= lo) ? src[jn] : lo;
+      int step[3];
+      const double chiB = rro_exit(&ray, m, hl, chiA, stop, step);
+      double corner[8][6];
+      memcpy(corner, cv + 48 * cur.cell, sizeof(corner));
+      double Q[9];
+      Q[0] = 0.0;
+      for (int i = 1; i <= 8; ++i) Q[i] = rro_quantity(&ray, corner[i - 1]);
+      const double p1[3] = {(double)m[0] * hl, (double)m[1] * hl, (double)m[2] * hl};
+      double ma, mb;
+      rro_moments_trilinear_q(&ray, Q, p1, hl, chiA, chiB, &ma, &mb);
+      A += kappa_scale * ma;
+      B += kappa_scale * mb;
+      hv = rro_fnv_segment(hv, cur.cell, chiA, chiB);
+      ++count;
+      if (jn < n_src && src[jn] == chiB) {
+        pieces[(r * n_src + jn) * 2 + 0] = A;
+        pieces[(r * n_src + jn) * 2 + 1] = B;
+        A = 0.0;
+        B = 0.0;
+        ++jn;
+      }
+      if (chiB == lo) break;
+      int any = 0;
+      for (int a = 0; a < 3; ++a) any |= step[a];
+      chiA = chiB;
+      if (!any) continue;   /* stopped at a source inside the leaf */
+      for (int a = 0; a < 3; ++a)
+        if (step[a]) m[a] += (ray.n[a] > 0.0) ? -1 : 1;
+      loc_t q = descend(t, l, m);
+      if (q.level < l) {
+        for (int a = 0; a < 3; ++a) m[a] = fdiv(m[a], (int64_t)1 << (l - q.level));
+        l = q.level;
+      }
+      while (t->child_oct[q.cell] >= 0) {
+        int child = 0;
+        for (int a = 0; a < 3; ++a) {
+          int bit;
+          if (step[a])
+            bit = ray.n[a] > 0.0 ? 1 : 0;
+          else
+            bit = slab_child(&ray, a, m[a], l, chiA);
+          m[a] = 2 * m[a] + bit;
+          child |= bit << a;
+        }
+        q.cell = nbase + 8 * (int64_t)t->child_oct[q.cell] + child;
+        ++l;
+      }
+      cur = q;
+    }
+    moments[2 * r + 0] = A;
+    moments[2 * r + 1] = B;
+    if (hash) hash[r] = hv;
+    if (ncross) ncross[r] = count;
+    if (status) status[r] = st;
+  }
+  free(src);
+  return 0;
+}
