@@ -241,6 +241,48 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp,
                         const rr_bundle* bundles /* host */, int32_t n_bundles, void* kappa,
                         float* kappa_comp, int32_t* ray_status, rr_stream s);
 
+/* Many source distances in one walk (Sec. VII, Eqs. Isources, Isources1).
+ * The lensing kernel g = chi (chi_s - chi) / chi_s splits into chi and
+ * chi^2 / chi_s, so the walk integrates A = int chi Q and B = int chi^2 Q
+ * (Q the quantity of tp, trilinear vertex tensor, uniform grids) without a
+ * source distance, and stops at each of a list of them:
+ *  chi_src    host, n_src (1..4096) source distances in the length unit of
+ *             the field, strictly decreasing.  A call stops at the sources
+ *             with chi_lo <= chi_src[j] < chi_hi of its bundle window; a
+ *             source inside a cell cuts that cell into two pieces (each is
+ *             hashed and counted like a crossing).
+ *  moments    device, per ray, in/out: the two integrals accumulated since
+ *             the last stop, times kappa_scale, in base-cell units.
+ *             FP32_KAHAN: 4 floats {A, A_comp, B, B_comp} (Kahan pairs);
+ *             FP64: 2 doubles {A, B}.  Start from zeros.
+ *  pieces     device, n_rays x n_src x 2 doubles: at the stop of source j
+ *             the walk writes the pair accumulated since the previous stop
+ *             (for FP32_KAHAN, sum minus compensation in FP64) and restarts
+ *             the moments from zero; entries of sources not met are left as
+ *             they are.
+ *  ray_status as in rr_trace_rays.
+ * Each bundle's chi_s is not used beyond the window check (give the
+ * farthest source).  Traced over consecutive windows down to chi_lo = 0,
+ * rr_kappa_from_pieces then gives kappa (or the shear) of every source.
+ * moments and pieces may be NULL when no bundle has rays.
+ * Debug outputs as in tp.  The source list is uploaded on first use
+ * (synchronously, outside graph capture) and kept by the plan.  Octree
+ * tensors, NGP and Method A return RR_ERR_UNSUPPORTED. */
+rr_status rr_trace_rays_sources(rr_plan p, rr_tensor t, const rr_trace_params* tp,
+                                const rr_bundle* bundles, int32_t n_bundles,
+                                const double* chi_src, int32_t n_src, void* moments,
+                                double* pieces, int32_t* ray_status, rr_stream s);
+
+/* kappa (FP64, n_rays x n_src, ray-major) of every source once the walk of
+ * rr_trace_rays_sources has reached the observer: A and B below source j
+ * are the moments left after the last stop plus the pieces of the sources
+ * nearer than j (Eq. Isources1), and kappa_j = A_j - B_j / chi_src[j]
+ * (Eq. Isources).  Sums in FP64; n_rays counts every ray of the arrays.
+ * Asynchronous on s; the source list is uploaded like rr_trace_rays_sources. */
+rr_status rr_kappa_from_pieces(rr_plan p, rr_tensor t, const double* chi_src, int32_t n_src,
+                               int64_t n_rays, const void* moments, const double* pieces,
+                               double* kappa, rr_stream s);
+
 /* The vertex box (lo, size as taken by rr_build_tidal_tensor_box) that
  * contains every vertex the rays of these bundles read between their chi_lo
  * and chi_hi: the lattice bounds of the rays' end points, widened by the

@@ -337,6 +337,63 @@ def trace(plan: Plan, tensor: TidalTensor, bundles: Sequence[RayBundle], observe
     return TraceOutput(kappa, kappa_comp, status, hsh, cnt, log)
 
 
+class SourcesOutput:
+    """State of the many-source walk: per-ray moments (FP32 Kahan pairs
+    {A, A_comp, B, B_comp} or FP64 {A, B}), pieces (n_rays, n_src, 2) FP64,
+    status and optional debug outputs."""
+
+    def __init__(self, moments, pieces, status, hash=None, count=None):
+        self.moments, self.pieces, self.status = moments, pieces, status
+        self.hash, self.count = hash, count
+
+
+def _src_array(chi_src):
+    src = np.ascontiguousarray(np.asarray(chi_src, dtype=np.float64).reshape(-1))
+    return src, src.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def trace_sources(plan: Plan, tensor: TidalTensor, bundles: Sequence[RayBundle], observer,
+                  chi_src, *, state: Optional[SourcesOutput] = None, kappa_scale: float = 1.0,
+                  quantity="kappa", persistent: int = -1, max_crossings: int = 0,
+                  debug: bool = False, stream=None) -> SourcesOutput:
+    """rr_trace_rays_sources: one walk for every source distance in ``chi_src``
+    (decreasing).  Pass the previous window's ``state`` to continue it."""
+    nr = total_rays(bundles)
+    fp32 = tensor.precision == A.PREC_FP32_KAHAN
+    dev = "cuda"
+    src, src_p = _src_array(chi_src)
+    if state is None:
+        mom = torch.zeros((nr, 4) if fp32 else (nr, 2),
+                          dtype=torch.float32 if fp32 else torch.float64, device=dev)
+        pcs = torch.zeros((nr, len(src), 2), dtype=torch.float64, device=dev)
+        state = SourcesOutput(mom, pcs, torch.zeros(nr, dtype=torch.int32, device=dev))
+    hsh = cnt = None
+    if debug:
+        hsh = torch.zeros(nr, dtype=torch.int64, device=dev)
+        cnt = torch.zeros(nr, dtype=torch.int64, device=dev)
+    tp = _params(observer, tensor.precision, quantity, kappa_scale, persistent, max_crossings,
+                 hsh, cnt, None, 0)
+    arr = _bundle_array(bundles)
+    A.check("rr_trace_rays_sources",
+            _lib.rr_trace_rays_sources(plan.handle, tensor.handle, C.byref(tp), arr, len(bundles),
+                                       src_p, len(src), _ptr(state.moments), _ptr(state.pieces),
+                                       _ptr(state.status), _stream(stream)))
+    return SourcesOutput(state.moments, state.pieces, state.status, hsh, cnt)
+
+
+def kappa_from_pieces(plan: Plan, tensor: TidalTensor, chi_src, state: SourcesOutput,
+                      stream=None) -> torch.Tensor:
+    """rr_kappa_from_pieces: (n_rays, n_src) FP64 kappa of every source."""
+    src, src_p = _src_array(chi_src)
+    nr = state.moments.shape[0]
+    out = torch.empty((nr, len(src)), dtype=torch.float64, device=state.moments.device)
+    A.check("rr_kappa_from_pieces",
+            _lib.rr_kappa_from_pieces(plan.handle, tensor.handle, src_p, len(src), nr,
+                                      _ptr(state.moments), _ptr(state.pieces), _ptr(out),
+                                      _stream(stream)))
+    return out
+
+
 def log_to_numpy(log: torch.Tensor) -> np.ndarray:
     """Convert a crossing log tensor (n, stride, 3 x 8 bytes) to records."""
     return log.cpu().numpy().view(LOG_DTYPE).reshape(log.shape[0], log.shape[1])

@@ -70,6 +70,13 @@ struct CachedTable {
   int64_t n_tiles = 0;
 };
 
+// A source-distance list (many-source walk) on the device, base-cell units.
+struct CachedSources {
+  std::vector<double> key;   // as given, box units
+  double h0 = 0.0;
+  double* dev = nullptr;
+};
+
 // Launch shape chosen by rr_plan_autotune for one bundle set.
 struct TunedShape {
   std::vector<rr_bundle> key;
@@ -91,6 +98,7 @@ struct rr_plan_s {
   int prefer_persistent = 0; // default when the caller passes persistent = -1
   int device = 0;
   std::vector<TunedShape> tuned;
+  std::vector<CachedSources> sources;
 };
 
 namespace {
@@ -313,6 +321,8 @@ rr_status rr_plan_destroy(rr_plan p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   for (auto& c : p->tables)
     if (c.dev) (void)hipFree(c.dev);
+  for (auto& c : p->sources)
+    if (c.dev) (void)hipFree(c.dev);
   if (p->queue) (void)hipFree(p->queue);
   delete p;
   return RR_OK;
@@ -439,6 +449,53 @@ rr_status get_table(rr_plan p, rr_tensor t, const rr_bundle* b, int32_t nb, int 
   return RR_OK;
 }
 
+constexpr int32_t kMaxSources = 4096;
+
+rr_status validate_sources(const double* chi_src, int32_t n_src) {
+  if (!chi_src) return fail(RR_ERR_INVALID_ARG, "chi_src is NULL");
+  if (n_src < 1 || n_src > kMaxSources)
+    return fail(RR_ERR_INVALID_ARG, "n_src %d outside [1, %d]", n_src, kMaxSources);
+  for (int32_t j = 0; j < n_src; ++j) {
+    if (!std::isfinite(chi_src[j])) return fail(RR_ERR_NONFINITE, "chi_src[%d] is not finite", j);
+    if (!(chi_src[j] > 0.0)) return fail(RR_ERR_INVALID_ARG, "chi_src[%d] must be > 0", j);
+    if (j > 0 && !(chi_src[j] < chi_src[j - 1]))
+      return fail(RR_ERR_INVALID_ARG, "chi_src must be strictly decreasing (index %d)", j);
+  }
+  return RR_OK;
+}
+
+// Find or upload the device copy of a source list in the tensor's cell units.
+rr_status get_sources(rr_plan p, rr_tensor t, const double* chi_src, int32_t n_src,
+                      hipStream_t s, const double** out) {
+  const double h0 = t->box / (double)t->n;
+  for (auto& c : p->sources) {
+    if (c.h0 == h0 && (int32_t)c.key.size() == n_src &&
+        std::memcmp(c.key.data(), chi_src, sizeof(double) * n_src) == 0) {
+      *out = c.dev;
+      return RR_OK;
+    }
+  }
+  if (capturing(s))
+    return fail(RR_ERR_CAPACITY,
+                "source list not uploaded before graph capture: run the call once first");
+  if (p->sources.size() >= 64) return fail(RR_ERR_CAPACITY, "plan holds 64 source lists already");
+  CachedSources c;
+  c.key.assign(chi_src, chi_src + n_src);
+  c.h0 = h0;
+  std::vector<double> host(n_src);
+  for (int32_t j = 0; j < n_src; ++j) host[j] = chi_src[j] / h0;
+  hipError_t e = hipMalloc((void**)&c.dev, sizeof(double) * n_src);
+  if (e != hipSuccess) return fail(RR_ERR_OOM, "source list: %s", hipGetErrorString(e));
+  e = hipMemcpy(c.dev, host.data(), sizeof(double) * n_src, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(c.dev);
+    return hip_fail(e, "source list upload");
+  }
+  p->sources.push_back(std::move(c));
+  *out = p->sources.back().dev;
+  return RR_OK;
+}
+
 }  // namespace
 
 }  // extern "C"
@@ -447,7 +504,8 @@ namespace {
 
 rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
                        int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
-                       hipStream_t hs, int persistent, int block, int waves_per_cu);
+                       hipStream_t hs, int persistent, int block, int waves_per_cu,
+                       const double* src = nullptr, int32_t n_src = 0, double* pieces = nullptr);
 
 const TunedShape* find_tuned(rr_plan p, const rr_bundle* b, int32_t nb) {
   for (const auto& x : p->tuned)
@@ -482,6 +540,62 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp, const
   }
   return launch_trace(p, t, tp, bundles, n_bundles, kappa, kappa_comp, ray_status, hs, persistent,
                       block, waves_per_cu);
+}
+
+rr_status rr_trace_rays_sources(rr_plan p, rr_tensor t, const rr_trace_params* tp,
+                                const rr_bundle* bundles, int32_t n_bundles,
+                                const double* chi_src, int32_t n_src, void* moments,
+                                double* pieces, int32_t* ray_status, rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  rr_status st = validate_trace(t, tp, bundles, n_bundles);
+  if (st != RR_OK) return st;
+  st = validate_sources(chi_src, n_src);
+  if (st != RR_OK) return st;
+  bool any_rays = false;
+  for (int32_t i = 0; i < n_bundles; ++i) any_rays |= bundles[i].n_rays > 0;
+  if (any_rays && !moments) return fail(RR_ERR_INVALID_ARG, "moments is NULL");
+  if (any_rays && !pieces) return fail(RR_ERR_INVALID_ARG, "pieces is NULL");
+  if (t->method_a || tp->integral != RR_INTEGRAL_TRILINEAR)
+    return fail(RR_ERR_UNSUPPORTED,
+                "the many-source walk integrates the tidal tensor with the trilinear integral");
+  if (t->kind != RR_GRID_UNIFORM)
+    return fail(RR_ERR_UNSUPPORTED, "the many-source walk is implemented for uniform grids");
+  const hipStream_t hs = (hipStream_t)s;
+  const double* src = nullptr;
+  st = get_sources(p, t, chi_src, n_src, hs, &src);
+  if (st != RR_OK) return st;
+  int persistent = tp->persistent < 0 ? p->prefer_persistent : (tp->persistent ? 1 : 0);
+  int block = 256, waves_per_cu = p->waves_per_cu;
+  if (tp->persistent < 0) {
+    if (const TunedShape* ts = find_tuned(p, bundles, n_bundles)) {
+      persistent = ts->persistent;
+      block = ts->block;
+      waves_per_cu = ts->waves_per_cu;
+    }
+  }
+  return launch_trace(p, t, tp, bundles, n_bundles, moments, nullptr, ray_status, hs, persistent,
+                      block, waves_per_cu, src, n_src, pieces);
+}
+
+rr_status rr_kappa_from_pieces(rr_plan p, rr_tensor t, const double* chi_src, int32_t n_src,
+                               int64_t n_rays, const void* moments, const double* pieces,
+                               double* kappa, rr_stream s) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  rr_status st = validate_sources(chi_src, n_src);
+  if (st != RR_OK) return st;
+  if (n_rays < 0) return fail(RR_ERR_INVALID_ARG, "n_rays is negative");
+  if (n_rays == 0) return RR_OK;
+  if (!moments || !pieces || !kappa)
+    return fail(RR_ERR_INVALID_ARG, "moments, pieces and kappa must be non-NULL");
+  const hipStream_t hs = (hipStream_t)s;
+  const double* src = nullptr;
+  st = get_sources(p, t, chi_src, n_src, hs, &src);
+  if (st != RR_OK) return st;
+  RR_HIP(rr::launch_kappa_from_pieces(t->precision, moments, pieces, src, n_src, n_rays, kappa,
+                                      hs),
+         "kappa from pieces launch");
+  return RR_OK;
 }
 
 rr_status rr_rays_vertex_box(rr_plan p, rr_tensor t, const rr_trace_params* tp,
@@ -624,7 +738,8 @@ namespace {
 
 rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
                        int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
-                       hipStream_t hs, int persistent, int block, int waves_per_cu) {
+                       hipStream_t hs, int persistent, int block, int waves_per_cu,
+                       const double* src, int32_t n_src, double* pieces) {
   rr_status st;
   const CachedTable* tab = nullptr;
   st = get_table(p, t, bundles, n_bundles, persistent, hs, &tab);
@@ -643,6 +758,12 @@ rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const 
   a.quantity = tp->quantity;
   a.integral = tp->integral;
   a.mode = t->method_a ? 2 : (tp->integral == RR_INTEGRAL_NGP ? 1 : 0);
+  if (src) {
+    a.mode = 3;
+    a.src = src;
+    a.n_src = n_src;
+    a.pieces = pieces;
+  }
   a.max_crossings = tp->max_crossings;
   a.kappa = kappa;
   a.kappa_comp = kappa_comp;

@@ -30,7 +30,8 @@ struct TraceArgs {
   int32_t open;              // RR_BOUNDARY_OPEN
   int32_t quantity;
   int32_t integral;
-  int32_t mode;              // integrand: 0 tidal tensor, 1 tidal tensor at centres (NGP), 2 Method A
+  int32_t mode;              // integrand: 0 tidal tensor, 1 tidal tensor at centres (NGP),
+                             // 2 Method A, 3 the two source-distance moments
   int64_t max_crossings;
   // outputs
   void* kappa;
@@ -42,6 +43,12 @@ struct TraceArgs {
   int64_t log_stride;
   // work queue (persistent mode)
   unsigned long long* queue;
+  // source-distance moments (mode 3): kappa holds the per-ray moment state,
+  // src the source distances (base-cell units, decreasing), pieces the pairs
+  // handed out at each of them
+  const double* src;
+  int32_t n_src;
+  double* pieces;
 };
 
 // Uniform vertex tensor record: 6 components, FP32 (24 B, three 8-byte
@@ -75,5 +82,9 @@ hipError_t launch_ray_bounds(const TraceArgs& a, int* out, hipStream_t s);
 hipError_t launch_march_uniform(int precision, const void* tv, const TraceArgs& a, int persistent,
                                 int block, int grid_waves, hipStream_t s);
 hipError_t launch_queue_reset(unsigned long long* q, hipStream_t s);
+// kappa of every source from the moment state and the pieces (mode 3)
+hipError_t launch_kappa_from_pieces(int precision, const void* moments, const double* pieces,
+                                    const double* src, int n_src, int64_t n_rays, double* kappa,
+                                    hipStream_t s);
 
 }  // namespace rr

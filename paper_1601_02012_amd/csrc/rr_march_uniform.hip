@@ -50,8 +50,9 @@ __device__ __forceinline__ R project(const R* __restrict__ tv, Off off, const R*
 }
 
 // Integrand modes: the tidal tensor with the trilinear integral, the tidal
-// tensor at cell centres (NGP), and Method A's (c delta, grad Phi) fields.
-constexpr int kTidal = 0, kNgp = 1, kMethodA = 2;
+// tensor at cell centres (NGP), Method A's (c delta, grad Phi) fields, and
+// the tidal tensor against the two source-distance moments chi and chi^2.
+constexpr int kTidal = 0, kNgp = 1, kMethodA = 2, kSources = 3;
 
 // Corner value(s) of the record at `off`: Q = P : T (tidal modes), or
 // (c delta, n . grad Phi) with P[0..2] = n (Method A).
@@ -208,7 +209,24 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   const R scale = (R)a.kappa_scale;
   R sum;
   float comp = 0.0f;
-  if constexpr (sizeof(R) == 4) {
+  // source-distance moments: (sum, comp) integrate chi Q, (sum2, comp2)
+  // chi^2 Q; the walk also stops at the next source distance src_j
+  R sum2 = 0;
+  float comp2 = 0.0f;
+  int jn = 0;
+  double src_j = -1.0;
+  if constexpr (kMode == kSources) {
+    if constexpr (sizeof(R) == 4) {
+      const float4 m = reinterpret_cast<const float4*>(a.kappa)[out];
+      sum = m.x; comp = m.y; sum2 = m.z; comp2 = m.w;
+    } else {
+      const double2 m = reinterpret_cast<const double2*>(a.kappa)[out];
+      sum = m.x; sum2 = m.y;
+    }
+    // this window stops at the sources with chi_lo <= chi_s,j < chi_hi
+    while (jn < a.n_src && !(a.src[jn] < chiA)) ++jn;
+    src_j = jn < a.n_src ? a.src[jn] : -1.0;
+  } else if constexpr (sizeof(R) == 4) {
     sum = reinterpret_cast<float*>(a.kappa)[out];
     if (a.kappa_comp) comp = a.kappa_comp[out];
   } else {
@@ -237,7 +255,9 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
       break;
     }
     // exit point: chi_B = max(chi_lo, t_exit,x, t_exit,y, t_exit,z), ties keep the earlier
+    // (the next source distance takes the place of chi_lo when it lies above it)
     double chiB = lo;
+    if constexpr (kMode == kSources) chiB = src_j >= lo ? src_j : lo;
     chiB = te[0] > chiB ? te[0] : chiB;
     chiB = te[1] > chiB ? te[1] : chiB;
     chiB = te[2] > chiB ? te[2] : chiB;
@@ -250,8 +270,13 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
 #pragma unroll
     for (int k = 0; k < 3; ++k) fB[k] = (R)1 - absd[k] * (R)(chiB - te[k]);
     const R L = (R)(chiA - chiB);
-    R ic;
-    if constexpr (kMode == kMethodA) {
+    R ic, ic2 = 0;
+    if constexpr (kMode == kSources) {
+      R ma, mb;
+      cell_moments<R>(q, fA, fB, L, (R)chiB, ma, mb);
+      ic = ma * scale;
+      ic2 = mb * scale;
+    } else if constexpr (kMode == kMethodA) {
       // Eq. (kappa2): c delta against g, n . grad Phi against dg/dchi, and the
       // step's surface term -[g n . grad Phi] at its first and last point
       R s = cell_integral_a<R>(q, q2, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis);
@@ -284,8 +309,10 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     }
     if constexpr (sizeof(R) == 4) {
       kahan_add(sum, comp, ic);
+      if constexpr (kMode == kSources) kahan_add(sum2, comp2, ic2);
     } else {
       sum += ic;
+      if constexpr (kMode == kSources) sum2 += ic2;
     }
     if constexpr (kDebug) {
       // cell id = vertex id of its lower corner: the exit layer where n_a > 0
@@ -302,6 +329,17 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
       }
     }
     ++count;
+    if constexpr (kMode == kSources) {
+      if (src_j == chiB) {
+        // hand out the two integrals accumulated since the previous stop
+        double* pc = a.pieces + (out * a.n_src + jn) * 2;
+        pc[0] = (double)sum - (double)comp;
+        pc[1] = (double)sum2 - (double)comp2;
+        sum = 0; comp = 0.0f; sum2 = 0; comp2 = 0.0f;
+        ++jn;
+        src_j = jn < a.n_src ? a.src[jn] : -1.0;
+      }
+    }
     if (chiB == lo) break;
     // step every axis whose exit plane is at chi_B: the exit layer becomes
     // the entry layer, the next layer along the march the exit layer
@@ -326,9 +364,12 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
         }
       }
     }
+    const int n_stepped = (int)stepped[0] + (int)stepped[1] + (int)stepped[2];
     if constexpr (kMode == kNgp) {
       // one record per cell: nothing carried from cell to cell
-    } else if ((int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1) {
+    } else if (kMode == kSources && n_stepped == 0) {
+      // stopped at a source distance inside the cell: same corners
+    } else if (n_stepped == 1) {
       // one face crossed (axis k): keep its four values, load the new exit face,
       // whose corners F_j (j = i_a + 2 i_b over the two other axes a < b)
       const bool k0 = stepped[0], k1 = stepped[1];
@@ -365,7 +406,13 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     chiA = chiB;
   }
   if (!(sum == sum) || sum - sum != (R)0) st = RR_RAY_NONFINITE;
-  if constexpr (sizeof(R) == 4) {
+  if constexpr (kMode == kSources) {
+    if (!(sum2 == sum2) || sum2 - sum2 != (R)0) st = RR_RAY_NONFINITE;
+    if constexpr (sizeof(R) == 4)
+      reinterpret_cast<float4*>(a.kappa)[out] = make_float4(sum, comp, sum2, comp2);
+    else
+      reinterpret_cast<double2*>(a.kappa)[out] = make_double2(sum, sum2);
+  } else if constexpr (sizeof(R) == 4) {
     reinterpret_cast<float*>(a.kappa)[out] = sum;
     if (a.kappa_comp) a.kappa_comp[out] = comp;
   } else {
@@ -430,6 +477,36 @@ __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restr
 }
 
 __global__ void queue_reset_kernel(unsigned long long* q) { *q = 0ull; }
+
+// kappa of every source (Eqs. Isources, Isources1) once the walk has reached
+// the observer: the moment state holds what lies below the nearest source,
+// and summing the pieces from the observer outwards gives int chi Q and
+// int chi^2 Q below each source in turn, kappa_j = A_j - B_j / chi_s,j.
+// FP64 throughout; one thread per ray.
+template <typename R>
+__global__ __launch_bounds__(256) void kappa_from_pieces_kernel(const R* __restrict__ mom,
+                                                                const double* __restrict__ pieces,
+                                                                const double* __restrict__ src,
+                                                                int ns, int64_t nr,
+                                                                double* __restrict__ kappa) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nr) return;
+  double A, B;
+  if constexpr (sizeof(R) == 4) {
+    const float4 m = reinterpret_cast<const float4*>(mom)[r];
+    A = (double)m.x - (double)m.y;
+    B = (double)m.z - (double)m.w;
+  } else {
+    const double2 m = reinterpret_cast<const double2*>(mom)[r];
+    A = m.x;
+    B = m.y;
+  }
+  for (int j = ns - 1; j >= 0; --j) {
+    kappa[r * ns + j] = A - B / src[j];
+    A += pieces[(r * ns + j) * 2 + 0];
+    B += pieces[(r * ns + j) * 2 + 1];
+  }
+}
 
 // Lattice bounds of the rays' end points (the walk between them stays in the
 // box they span).  One wavefront per tile, reduced across the wavefront
@@ -508,6 +585,13 @@ hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block,
     return small ? launch3<R, false, uint32_t, kMethodA>(tv, a, persistent, block, grid_waves, s)
                  : launch3<R, false, uint64_t, kMethodA>(tv, a, persistent, block, grid_waves, s);
   }
+  if (a.mode == kSources) {
+    if (dbg)
+      return small ? launch3<R, true, uint32_t, kSources>(tv, a, persistent, block, grid_waves, s)
+                   : launch3<R, true, uint64_t, kSources>(tv, a, persistent, block, grid_waves, s);
+    return small ? launch3<R, false, uint32_t, kSources>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, false, uint64_t, kSources>(tv, a, persistent, block, grid_waves, s);
+  }
   if (a.mode == kNgp) {
     if (dbg)
       return small ? launch3<R, true, uint32_t, kNgp>(tv, a, persistent, block, grid_waves, s)
@@ -534,6 +618,20 @@ hipError_t launch_ray_bounds(const TraceArgs& a, int* out, hipStream_t s) {
   const int64_t blocks = (a.n_tiles + 3) / 4;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(ray_bounds_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_kappa_from_pieces(int precision, const void* moments, const double* pieces,
+                                    const double* src, int n_src, int64_t n_rays, double* kappa,
+                                    hipStream_t s) {
+  const int64_t blocks = (n_rays + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  if (precision == RR_PREC_FP32_KAHAN)
+    hipLaunchKernelGGL(kappa_from_pieces_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const float*)moments, pieces, src, n_src, n_rays, kappa);
+  else
+    hipLaunchKernelGGL(kappa_from_pieces_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const double*)moments, pieces, src, n_src, n_rays, kappa);
   return hipGetLastError();
 }
 

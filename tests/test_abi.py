@@ -77,4 +77,9 @@ def test_host_validation_without_gpu(abi):
     assert lib.rr_build_tidal_tensor_box(None, None, lo, lo, None) == -1
     assert "NULL" in abi.last_error()
     assert lib.rr_rays_vertex_box(None, None, None, None, 0, lo, lo, None) == -1
+    src = (C.c_double * 2)(5.0, 3.0)
+    assert lib.rr_trace_rays_sources(None, None, None, None, 0, src, 2, None, None, None,
+                                     None) == -1
+    assert lib.rr_kappa_from_pieces(None, None, src, 2, 1, None, None, None, None) == -1
+    assert "plan" in abi.last_error()
     assert lib.rr_version() >= 10000
