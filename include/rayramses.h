@@ -244,8 +244,9 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp,
 /* Many source distances in one walk (Sec. VII, Eqs. Isources, Isources1).
  * The lensing kernel g = chi (chi_s - chi) / chi_s splits into chi and
  * chi^2 / chi_s, so the walk integrates A = int chi Q and B = int chi^2 Q
- * (Q the quantity of tp, trilinear vertex tensor, uniform grids) without a
- * source distance, and stops at each of a list of them:
+ * (Q the quantity of tp, trilinear reconstruction from the vertex tensor or
+ * the octree's per-leaf corners) without a source distance, and stops at
+ * each of a list of them:
  *  chi_src    host, n_src (1..4096) source distances in the length unit of
  *             the field, strictly decreasing.  A call stops at the sources
  *             with chi_lo <= chi_src[j] < chi_hi of its bundle window; a
@@ -266,8 +267,8 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp,
  * rr_kappa_from_pieces then gives kappa (or the shear) of every source.
  * moments and pieces may be NULL when no bundle has rays.
  * Debug outputs as in tp.  The source list is uploaded on first use
- * (synchronously, outside graph capture) and kept by the plan.  Octree
- * tensors, NGP and Method A return RR_ERR_UNSUPPORTED. */
+ * (synchronously, outside graph capture) and kept by the plan.  NGP and
+ * Method A return RR_ERR_UNSUPPORTED. */
 rr_status rr_trace_rays_sources(rr_plan p, rr_tensor t, const rr_trace_params* tp,
                                 const rr_bundle* bundles, int32_t n_bundles,
                                 const double* chi_src, int32_t n_src, void* moments,

@@ -558,8 +558,6 @@ rr_status rr_trace_rays_sources(rr_plan p, rr_tensor t, const rr_trace_params* t
   if (t->method_a || tp->integral != RR_INTEGRAL_TRILINEAR)
     return fail(RR_ERR_UNSUPPORTED,
                 "the many-source walk integrates the tidal tensor with the trilinear integral");
-  if (t->kind != RR_GRID_UNIFORM)
-    return fail(RR_ERR_UNSUPPORTED, "the many-source walk is implemented for uniform grids");
   const hipStream_t hs = (hipStream_t)s;
   const double* src = nullptr;
   st = get_sources(p, t, chi_src, n_src, hs, &src);

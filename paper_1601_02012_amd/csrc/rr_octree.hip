@@ -355,6 +355,11 @@ __device__ __forceinline__ int descend_from(const Tree& T, Off b, int l, const i
   return l;
 }
 
+// Integrands: the tidal tensor with the trilinear integral, the leaf's
+// centre tensor (NGP), and the trilinear tensor against the two
+// source-distance moments chi and chi^2 (the many-source walk).
+constexpr int kOctTidal = 0, kOctNgp = 1, kOctSources = 3;
+
 // One ray through the octree, in the ray's frame (as the uniform march):
 // per axis the lane keeps, in FP64, the crossing parameter of the current
 // leaf's exit plane and the level-l coordinates m, and the local coordinate
@@ -367,7 +372,7 @@ __device__ __forceinline__ int descend_from(const Tree& T, Off b, int l, const i
 // with its child link; level changes and edge crossings reload all eight.
 // A crossing that stays on level 0 or inside the parent oct needs no walk
 // from the base cell.
-template <typename R, bool kDebug, bool kNgp, typename Off>
+template <typename R, bool kDebug, int kMode, typename Off>
 __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceArgs& a,
                           const DevBundle& B, int64_t ray) {
   const int64_t out = B.ray_offset + ray;
@@ -439,13 +444,29 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
 #pragma unroll
   for (int k = 0; k < 3; ++k) fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
   R q[8];
-  if constexpr (!kNgp) load_leaf<R, Off>(cv, cell, flip, P, q);
+  if constexpr (kMode != kOctNgp) load_leaf<R, Off>(cv, cell, flip, P, q);
 
   const R inv_chis = (R)(1.0 / B.chi_s);
   const R scale = (R)a.kappa_scale;
   R sum;
   float comp = 0.0f;
-  if constexpr (sizeof(R) == 4) {
+  // many-source walk: (sum, comp) integrate chi Q, (sum2, comp2) chi^2 Q, and
+  // the walk also stops at the next source distance src_j
+  R sum2 = 0;
+  float comp2 = 0.0f;
+  int jn = 0;
+  double src_j = -1.0;
+  if constexpr (kMode == kOctSources) {
+    if constexpr (sizeof(R) == 4) {
+      const float4 mm = reinterpret_cast<const float4*>(a.kappa)[out];
+      sum = mm.x; comp = mm.y; sum2 = mm.z; comp2 = mm.w;
+    } else {
+      const double2 mm = reinterpret_cast<const double2*>(a.kappa)[out];
+      sum = mm.x; sum2 = mm.y;
+    }
+    while (jn < a.n_src && !(a.src[jn] < chiA)) ++jn;
+    src_j = jn < a.n_src ? a.src[jn] : -1.0;
+  } else if constexpr (sizeof(R) == 4) {
     sum = reinterpret_cast<float*>(a.kappa)[out];
     if (a.kappa_comp) comp = a.kappa_comp[out];
   } else {
@@ -462,6 +483,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       break;
     }
     double chiB = lo;
+    if constexpr (kMode == kOctSources) chiB = src_j >= lo ? src_j : lo;
     chiB = te[0] > chiB ? te[0] : chiB;
     chiB = te[1] > chiB ? te[1] : chiB;
     chiB = te[2] > chiB ? te[2] : chiB;
@@ -470,11 +492,11 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
 
     const R L = (R)(chiA - chiB);
-    R ic;
+    R ic, ic2 = 0;
     R fB[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) fB[k] = (R)1 - absd[k] * (R)(chiB - te[k]);
-    if constexpr (kNgp) {
+    if constexpr (kMode == kOctNgp) {
       // Eq. (Iclensing_ngp): the leaf's centre value times the integral of g,
       // L (g(mid) - L^2 / (12 chi_s)) with g(chi) = chi (chi_s - chi) / chi_s
       const R* tc = cv + 6 * (uint64_t)cell;
@@ -484,13 +506,20 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       const double mid = chiB + 0.5 * (chiA - chiB);
       const R gm = (R)mid * (R)(B.chi_s - mid) - L * L * (R)(1.0 / 12.0);
       ic = Qc * (gm * L * inv_chis) * scale;
+    } else if constexpr (kMode == kOctSources) {
+      R ma, mb;
+      cell_moments<R>(q, fA, fB, L, (R)chiB, ma, mb);
+      ic = ma * scale;
+      ic2 = mb * scale;
     } else {
       ic = cell_integral<R>(q, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
     }
     if constexpr (sizeof(R) == 4) {
       kahan_add(sum, comp, ic);
+      if constexpr (kMode == kOctSources) kahan_add(sum2, comp2, ic2);
     } else {
       sum += ic;
+      if constexpr (kMode == kOctSources) sum2 += ic2;
     }
     if constexpr (kDebug) {
       if (a.hash) hv = fnv_piece(hv, (int64_t)cell, chiA, chiB);
@@ -502,8 +531,27 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       }
     }
     ++count;
+    if constexpr (kMode == kOctSources) {
+      if (src_j == chiB) {
+        // hand out the two integrals accumulated since the previous stop
+        double* pc = a.pieces + (out * a.n_src + jn) * 2;
+        pc[0] = (double)sum - (double)comp;
+        pc[1] = (double)sum2 - (double)comp2;
+        sum = 0; comp = 0.0f; sum2 = 0; comp2 = 0.0f;
+        ++jn;
+        src_j = jn < a.n_src ? a.src[jn] : -1.0;
+      }
+    }
     if (chiB == lo) break;
     chiA = chiB;
+    if constexpr (kMode == kOctSources) {
+      if (!(stepped[0] || stepped[1] || stepped[2])) {
+        // stopped at a source distance inside the leaf: same corners
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fA[k] = fB[k];
+        continue;
+      }
+    }
 
     // step the crossed axes on level l; track the base cell
     const int ch_old = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
@@ -542,7 +590,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     const bool single = (int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1;
     int kc = T.child[nc];
     bool kept = false;
-    if constexpr (!kNgp) {
+    if constexpr (kMode != kOctNgp) {
       if (lev == l && single) {
         const bool k0 = stepped[0], k1 = stepped[1];
         // slots of the new exit face: (1 << k) | i_a << a | i_b << b, a < b the other axes
@@ -588,7 +636,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         for (int k = 0; k < 3; ++k) m[k] >>= (l_in - lev);
         l = lev;
       }
-      if constexpr (!kNgp) load_leaf<R, Off>(cv, nc, flip, P, q);
+      if constexpr (kMode != kOctNgp) load_leaf<R, Off>(cv, nc, flip, P, q);
     }
     if (l != l_in) {
       set_level(l - l_in);
@@ -607,7 +655,13 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     cell = nc;
   }
   if (!(sum == sum) || sum - sum != (R)0) st = RR_RAY_NONFINITE;
-  if constexpr (sizeof(R) == 4) {
+  if constexpr (kMode == kOctSources) {
+    if (!(sum2 == sum2) || sum2 - sum2 != (R)0) st = RR_RAY_NONFINITE;
+    if constexpr (sizeof(R) == 4)
+      reinterpret_cast<float4*>(a.kappa)[out] = make_float4(sum, comp, sum2, comp2);
+    else
+      reinterpret_cast<double2*>(a.kappa)[out] = make_double2(sum, sum2);
+  } else if constexpr (sizeof(R) == 4) {
     reinterpret_cast<float*>(a.kappa)[out] = sum;
     if (a.kappa_comp) a.kappa_comp[out] = comp;
   } else {
@@ -620,7 +674,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   }
 }
 
-template <typename R, bool kDebug, bool kNgp, typename Off>
+template <typename R, bool kDebug, int kMode, typename Off>
 __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -628,10 +682,10 @@ __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const Trace
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kNgp, Off>(T, cv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kMode, Off>(T, cv, a, B, (int64_t)iy * B.nx + ix);
 }
 
-template <typename R, bool kDebug, bool kNgp, typename Off>
+template <typename R, bool kDebug, int kMode, typename Off>
 __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __restrict__ cv,
                                                            TraceArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -641,11 +695,10 @@ __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __re
   const int64_t tile =
       ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
-  oct_tile<R, kDebug, kNgp, Off>(T, cv, a, tile, lane);
+  oct_tile<R, kDebug, kMode, Off>(T, cv, a, tile, lane);
 }
 
-// FP32: four waves per SIMD (at most 128 VGPRs) fit without spills
-template <typename R, bool kDebug, bool kNgp, typename Off>
+template <typename R, bool kDebug, int kMode, typename Off>
 __global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* __restrict__ cv, TraceArgs a) {
   const int lane = threadIdx.x & 63;
   for (;;) {
@@ -655,22 +708,22 @@ __global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* 
     const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
     if (tile >= a.n_tiles) break;
-    oct_tile<R, kDebug, kNgp, Off>(T, cv, a, tile, lane);
+    oct_tile<R, kDebug, kMode, Off>(T, cv, a, tile, lane);
   }
 }
 
-template <typename R, bool kDebug, bool kNgp, typename Off>
+template <typename R, bool kDebug, int kMode, typename Off>
 hipError_t launch_march(const Tree& T, const void* cv, const TraceArgs& a, int persistent,
                         int grid_waves, hipStream_t s) {
   if (persistent) {
     const int blocks = (grid_waves + 3) / 4;
-    hipLaunchKernelGGL((march_octree_persistent<R, kDebug, kNgp, Off>), dim3(blocks), dim3(256), 0, s, T,
+    hipLaunchKernelGGL((march_octree_persistent<R, kDebug, kMode, Off>), dim3(blocks), dim3(256), 0, s, T,
                        (const R*)cv, a);
   } else {
     int64_t blocks = (a.n_tiles + 3) / 4;
     if (blocks == 0) return hipSuccess;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL((march_octree_kernel<R, kDebug, kNgp, Off>), dim3((unsigned)blocks), dim3(256), 0, s,
+    hipLaunchKernelGGL((march_octree_kernel<R, kDebug, kMode, Off>), dim3((unsigned)blocks), dim3(256), 0, s,
                        T, (const R*)cv, a);
   }
   return hipGetLastError();
@@ -713,17 +766,17 @@ hipError_t OctreeTensor::build(const void* values, int dtype, hipStream_t s) {
 
 namespace {
 
-template <typename R, bool kNgp>
+template <typename R, int kMode>
 hipError_t launch_march_w(const Tree& T, const void* cv, int64_t n_cells, const TraceArgs& a,
                           int persistent, int grid_waves, hipStream_t s) {
   const bool dbg = a.hash || a.log || a.count;
   // 32-bit cell indices and byte offsets when the corner blocks are below 4 GiB
   const bool small = n_cells * 48 * (int64_t)sizeof(R) < (1ll << 32);
   if (small)
-    return dbg ? launch_march<R, true, kNgp, uint32_t>(T, cv, a, persistent, grid_waves, s)
-               : launch_march<R, false, kNgp, uint32_t>(T, cv, a, persistent, grid_waves, s);
-  return dbg ? launch_march<R, true, kNgp, uint64_t>(T, cv, a, persistent, grid_waves, s)
-             : launch_march<R, false, kNgp, uint64_t>(T, cv, a, persistent, grid_waves, s);
+    return dbg ? launch_march<R, true, kMode, uint32_t>(T, cv, a, persistent, grid_waves, s)
+               : launch_march<R, false, kMode, uint32_t>(T, cv, a, persistent, grid_waves, s);
+  return dbg ? launch_march<R, true, kMode, uint64_t>(T, cv, a, persistent, grid_waves, s)
+             : launch_march<R, false, kMode, uint64_t>(T, cv, a, persistent, grid_waves, s);
 }
 
 }  // namespace
@@ -732,14 +785,19 @@ hipError_t OctreeTensor::march(const TraceArgs& a, int persistent, int grid_wave
                                hipStream_t s) {
   if (a.n_tiles == 0) return hipSuccess;
   Tree T{child_oct_dev, reinterpret_cast<const int4*>(oct_info), n, (int64_t)n * n * n};
-  if (a.mode == 1) {   // NGP: cell-centre records, 6 per cell
+  if (a.mode == kOctNgp) {   // cell-centre records, 6 per cell
     if (precision == RR_PREC_FP32_KAHAN)
-      return launch_march_w<float, true>(T, centre, n_cells, a, persistent, grid_waves, s);
-    return launch_march_w<double, true>(T, centre, n_cells, a, persistent, grid_waves, s);
+      return launch_march_w<float, kOctNgp>(T, centre, n_cells, a, persistent, grid_waves, s);
+    return launch_march_w<double, kOctNgp>(T, centre, n_cells, a, persistent, grid_waves, s);
+  }
+  if (a.mode == kOctSources) {
+    if (precision == RR_PREC_FP32_KAHAN)
+      return launch_march_w<float, kOctSources>(T, corners, n_cells, a, persistent, grid_waves, s);
+    return launch_march_w<double, kOctSources>(T, corners, n_cells, a, persistent, grid_waves, s);
   }
   if (precision == RR_PREC_FP32_KAHAN)
-    return launch_march_w<float, false>(T, corners, n_cells, a, persistent, grid_waves, s);
-  return launch_march_w<double, false>(T, corners, n_cells, a, persistent, grid_waves, s);
+    return launch_march_w<float, kOctTidal>(T, corners, n_cells, a, persistent, grid_waves, s);
+  return launch_march_w<double, kOctTidal>(T, corners, n_cells, a, persistent, grid_waves, s);
 }
 
 }  // namespace rr

@@ -185,3 +185,61 @@ def test_empty_bundle_and_rejected_arguments(api, plan, c1):
     with pytest.raises(api.RRError):
         api.trace_sources(plan, tc, [gb], c1.observer, SOURCES)           # NGP records
     tc.close()
+
+
+# ---------------------------------------------------------------- octree --
+@pytest.fixture(scope="module")
+def tree_case():
+    from tests.test_gpu_octree import _smooth_phi
+    rng = np.random.default_rng(41)
+    t = I.random_octree(12, 3, 0.2, rng, region=(2.0, 10.0))
+    box = 24.0
+    return t, box, _smooth_phi(t, box, rng)
+
+
+OCT_SOURCES = np.array([60.0, 47.3, 31.05, 20.0, 8.8, 0.9])
+OCT_WINDOWS = [(60.0, 20.0), (20.0, 0.0)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_octree_sources_match_oracle(api, oracle, plan, tree_case, prec):
+    """Multi-level octree: cut crossing hashes bit-exact per window, FP64
+    pieces to 1e-11 of their scale, FP32-Kahan kappa of every source within
+    max(1e-5 |kappa|, 1e-7) of the oracle's single-source octree trace."""
+    import torch
+    from tests.test_gpu_octree import _gpu_octree_grid, _otree
+    t, box, phi = tree_case
+    dt = np.float64 if prec == "fp64" else np.float32
+    tt = api.TidalTensor(_gpu_octree_grid(api, t, phi, box, dt), prec).build()
+    fov = math.radians(50.0)
+    nx, ny = 21, 13
+    dirs = I.fov_directions((0.2, 0.1, 1.0), fov, fov * 0.6, nx, ny)
+    obs = (11.7, 12.2, 3.1)
+    ot = _otree(oracle, t)
+    p64 = phi.astype(dt).astype(np.float64)
+    cv = oracle.corner_tensor_octree(ot, oracle.centre_tensor_octree(ot, p64))
+    state = None
+    mom = pcs = None
+    for hi, lo in OCT_WINDOWS:
+        b = api.RayBundle(torch.as_tensor(dirs).cuda(), nx, ny, OCT_SOURCES[0], hi, lo)
+        state = api.trace_sources(plan, tt, [b], obs, OCT_SOURCES, state=state, debug=True)
+        r = oracle.trace_octree_sources(ot, box, obs, dirs, hi, lo, OCT_SOURCES, cv=cv,
+                                        moments=mom, pieces=pcs)
+        mom, pcs = r.moments, r.pieces
+        assert np.all(state.status.cpu().numpy() == 0)
+        assert np.array_equal(state.count.cpu().numpy(), r.ncross)
+        assert np.array_equal(hashes_u64(state.hash), r.hash)
+    kap = api.kappa_from_pieces(plan, tt, OCT_SOURCES, state).cpu().numpy()
+    if prec == "fp64":
+        got = state.pieces.cpu().numpy()
+        for c in range(2):
+            np.testing.assert_allclose(got[..., c], pcs[..., c], rtol=0,
+                                       atol=1e-11 * np.abs(pcs[..., c]).max())
+        ref = oracle.kappa_from_pieces(OCT_SOURCES, box, t.n, mom, pcs)
+        np.testing.assert_allclose(kap, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    else:
+        for j, cs in enumerate(OCT_SOURCES):
+            ref = oracle.trace_octree(ot, box, obs, dirs, cs, cs, 0.0, cv=cv)
+            ok, worst = kappa_tolerance_ok(kap[:, j], ref.kappa)
+            assert ok, (cs, worst)
+    tt.close()
