@@ -19,11 +19,11 @@
 // (plus a two-cell halo) in LDS; every thread reads its 4 x 4 patch of that
 // plane once and keeps the per-plane partial stencils of the last four planes
 // in registers, so each vertex costs 16 LDS reads and ~80 arithmetic
-// operations.  Whole-grid builds take 64 x 8 x 64 columns (the halo re-reads
-// 1.4 potential values per vertex) and write the records with non-temporal
-// stores (the 3 GiB tensor of a 512^3 grid does not fit any cache); small
-// boxes take 64 x 4 x 32 columns and ordinary stores, since the march reads
-// them right away.
+// operations.  Whole-grid builds take 64 x 16 x 16 columns (1024 threads;
+// staging with the halo reads 1.5 potential values per vertex) and write the
+// records with non-temporal stores (the 3 GiB tensor of a 512^3 grid does not
+// fit any cache); small boxes take 64 x 4 x 32 columns and ordinary stores,
+// since the march reads them right away.
 #include "rr_internal.hpp"
 
 namespace rr {
@@ -332,7 +332,7 @@ hipError_t launch_vt(int n, int open, const int* lo, const int* size, const void
   const int64_t nv = (int64_t)V.sx * V.sy * V.sz;
   // boxes beyond 1/8 of the grid stream through HBM like the whole grid
   if (8 * nv > (int64_t)n * n * n)
-    return launch_shape<In, Acc, 8, 64, true>(V, n, open, phi, tv, s);
+    return launch_shape<In, Acc, 16, 16, true>(V, n, open, phi, tv, s);
   return launch_shape<In, Acc, 4, 32, false>(V, n, open, phi, tv, s);
 }
 
