@@ -19,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle_rro.so")
 SOURCES = ["rro_uniform.c", "rro_adjoint.c", "rro_octree.c", "rro_method_a.c",
-           "rro_sources.c"]
+           "rro_sources.c", "rro_isw.c"]
 
 RAY_OK, RAY_OUT_OF_DOMAIN, RAY_MAX_STEPS = 0, 1, 2
 Q_KAPPA, Q_GAMMA1, Q_GAMMA2 = 0, 1, 2
@@ -93,6 +93,12 @@ def lib():
         L.rro_trace_octree_sources.restype = i32
         L.rro_kappa_from_pieces.argtypes = [i64, i32, vp, dbl, i32, vp, vp, vp]
         L.rro_cell_moments.argtypes = [vp, vp, dbl, vp, vp, dbl, dbl, vp]
+        L.rro_isw_vertex_field.argtypes = [i32, i32, vp, vp, dbl, vp]
+        L.rro_trace_uniform_isw.argtypes = [i32, i32, dbl, vp, i64, vp, vp, vp, dbl, vp, i64,
+                                            i32, vp, vp, vp, vp]
+        L.rro_trace_uniform_isw.restype = i32
+        L.rro_cell_integral_one.argtypes = [vp, vp, dbl, vp, vp, dbl, dbl]
+        L.rro_cell_integral_one.restype = dbl
         L.rro_projection.argtypes = [vp, vp, i32]
         L.rro_projection.restype = dbl
         _lib = L
@@ -266,6 +272,42 @@ def kappa_from_pieces(chi_src, box, n_base, moments, pieces):
     lib().rro_kappa_from_pieces(mom.shape[0], src.shape[0], _p(src), float(box), int(n_base),
                                 _p(mom), _p(pcs), _p(out))
     return out
+
+
+def isw_vertex_field(phi_curr, phi_prev, inv_dt, open_boundary=False):
+    """Vertex values of (phi_curr - phi_prev) * inv_dt (eight-cell mean); (n^3,)."""
+    pc = _f64(phi_curr)
+    pp = _f64(phi_prev)
+    n = pc.shape[0]
+    qv = np.empty(n ** 3)
+    lib().rro_isw_vertex_field(n, int(open_boundary), _p(pc), _p(pp), float(inv_dt), _p(qv))
+    return qv
+
+
+def trace_uniform_isw(n, box, observer, dirs, chi_hi, chi_lo, *, qv=None, phi_curr=None,
+                      phi_prev=None, inv_dt=1.0, open_boundary=False, scale=1.0,
+                      max_steps=1 << 40, threads=0) -> TraceResult:
+    """ISW integral scale * int Q dchi (box units) per ray, FP64; ``qv`` from
+    isw_vertex_field, or the two potentials to compute it here."""
+    dirs = _f64(dirs).reshape(-1, 3)
+    nr = dirs.shape[0]
+    if qv is None:
+        qv = isw_vertex_field(phi_curr, phi_prev, inv_dt, open_boundary)
+    out = np.zeros(nr)
+    hsh = np.zeros(nr, dtype=np.uint64)
+    ncr = np.zeros(nr, dtype=np.int64)
+    st = np.zeros(nr, dtype=np.int32)
+    lib().rro_trace_uniform_isw(n, int(open_boundary), float(box), _p(_f64(observer)), nr,
+                                _p(dirs), _p(_per_ray(chi_hi, nr)), _p(_per_ray(chi_lo, nr)),
+                                float(scale), _p(_f64(qv)), int(max_steps), int(threads),
+                                _p(out), _p(hsh), _p(ncr), _p(st))
+    return TraceResult(out, hsh, ncr, st, None)
+
+
+def cell_integral_one(Q, p1, h, direction, o, chi_a, chi_b):
+    """int Q dchi over one cell's piece (grid units)."""
+    return lib().rro_cell_integral_one(_p(_f64(Q)), _p(_f64(p1)), float(h), _p(_f64(direction)),
+                                       _p(_f64(o)), float(chi_a), float(chi_b))
 
 
 def trace_adjoint_uniform(n, box, observer, dirs, chi_s, chi_hi, chi_lo, dl_dkappa,

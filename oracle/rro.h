@@ -19,6 +19,7 @@
  *   per-cell lensing integral Eq. (Iclensing); NGP variant Eq. (Iclensing_ngp)
  *   kappa integrand          Eqs. (n1n1), (n2n2); shear Eqs. (gamma1), (gamma2), (n1n2)
  *   many source distances    Sec. VII, Eqs. (Isources), (Isources1)
+ *   ISW integrand            Sec. VII, Eq. (I1) with Q = dPhi/dt
  *
  * Units: lengths are converted to base-grid units, h0 = L / n_base,
  * o~ = o / h0, chi~ = chi / h0; a level-l cell has size 2^-l.  kappa is
@@ -117,6 +118,21 @@ void rro_cell_moments(const double* Q, const double* p1, double h, const double*
 void rro_kappa_from_pieces(int64_t n_rays, int32_t n_src, const double* chi_src, double box,
                            int32_t n_base, const double* moments, const double* pieces,
                            double* kappa);
+
+/* ISW integrand (Sec. VII; Eq. I1 with Q = dPhi/dt): vertex values of
+ * (phi_curr - phi_prev) * inv_dt (mean of the eight incident cells), then
+ * out = scale * int Q dchi per ray over [chi_lo, chi_hi] (box units; the
+ * kernel is the constant scale within a step). */
+void rro_isw_vertex_field(int32_t n, int32_t open, const double* phi_curr,
+                          const double* phi_prev, double inv_dt, double* qv /* n^3 */);
+int32_t rro_trace_uniform_isw(int32_t n, int32_t open, double box, const double* observer,
+                              int64_t n_rays, const double* dir, const double* chi_hi,
+                              const double* chi_lo, double scale, const double* qv,
+                              int64_t max_steps, int32_t n_threads, double* out, uint64_t* hash,
+                              int64_t* ncross, int32_t* status);
+/* int Q dchi over one cell's piece [chi_B, chi_A] (grid units). */
+double rro_cell_integral_one(const double* Q, const double* p1, double h, const double* dir,
+                             const double* o, double chiA, double chiB);
 
 /* Adjoint of kappa = A(Phi) for a uniform grid: dL/dPhi += A^T (dL/dkappa).
  * Explicit transpose of: per-cell integral -> vertex average -> FD stencil. */
