@@ -67,8 +67,11 @@ typedef enum { RR_GRID_UNIFORM = 0, RR_GRID_OCTREE = 1 } rr_grid_kind;
 /* RR_FIELD_PHI: the potential (Method B, Eq. kappa; also Method A's gradient
  * term).  RR_FIELD_DELTA: the density contrast of Method A's Poisson term
  * (Eq. kappa2), uniform grids only; a tensor created from it holds Method A
- * vertex fields (rr_build_method_a_fields). */
-typedef enum { RR_FIELD_PHI = 0, RR_FIELD_DELTA = 1 } rr_field_kind;
+ * vertex fields (rr_build_method_a_fields).  RR_FIELD_PHI_DOT: the rate of
+ * change of the potential for the ISW integrand (Sec. VII), uniform grids
+ * only; a tensor created from it holds one scalar per vertex
+ * (rr_build_isw_field); values are not read at creation. */
+typedef enum { RR_FIELD_PHI = 0, RR_FIELD_DELTA = 1, RR_FIELD_PHI_DOT = 2 } rr_field_kind;
 /* PERIODIC: the grid is one period of a replicated box (the paper's tiled
  * boxes, Sec. III B, with one realization).  OPEN: no wrap; cells on the two
  * outer layers only feed stencils, and a ray entering a cell outside
@@ -80,8 +83,10 @@ typedef enum { RR_BOUNDARY_PERIODIC = 0, RR_BOUNDARY_OPEN = 1 } rr_boundary;
 typedef enum { RR_PREC_FP64 = 0, RR_PREC_FP32_KAHAN = 1 } rr_precision;
 typedef enum { RR_F32 = 0, RR_F64 = 1 } rr_dtype;
 /* Integrand: kappa (Eq. kappa), gamma_1 (Eq. gamma1), gamma_2 (Eq. gamma2 with
- * the mixed projection e_phi^T T e_theta). */
-typedef enum { RR_Q_KAPPA = 0, RR_Q_GAMMA1 = 1, RR_Q_GAMMA2 = 2 } rr_quantity;
+ * the mixed projection e_phi^T T e_theta); RR_Q_SCALAR: the vertex scalar of
+ * an ISW tensor integrated with a constant kernel (the only quantity such a
+ * tensor takes). */
+typedef enum { RR_Q_KAPPA = 0, RR_Q_GAMMA1 = 1, RR_Q_GAMMA2 = 2, RR_Q_SCALAR = 3 } rr_quantity;
 /* Per-cell integral: trilinear vertex reconstruction (Eq. Iclensing, the
  * tensor holds vertex records: rr_build_tidal_tensor) or the
  * nearest-grid-point value of the cell centre times the integrated kernel
@@ -155,6 +160,20 @@ rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s
  * and dtype of the tensor.  Asynchronous on s; no allocation. */
 rr_status rr_build_method_a_fields(rr_tensor t, const rr_field_desc* delta,
                                    const rr_field_desc* phi, double delta_coeff, rr_stream s);
+
+/* ISW integrand (Sec. VII: Eq. I1 with Q the time derivative of the
+ * potential, by finite differences between N-body steps).  The tensor is
+ * created from a descriptor with field RR_FIELD_PHI_DOT (uniform grids) and
+ * holds per vertex the mean over its eight cells of
+ * (phi_curr - phi_prev) * inv_dt (Sec. III F); open grids leave the vertices
+ * on the lower faces NaN.  rr_trace_rays with quantity RR_Q_SCALAR and the
+ * trilinear integral then adds kappa_scale * int Q dchi (chi in the box's
+ * length unit) per ray over its window: the paper gives no kernel K for this
+ * case, so it is the constant kappa_scale of the step (e.g. 2 a / c in the
+ * units of inv_dt).  phi_curr and phi_prev share the grid, boundary and
+ * dtype of the tensor.  Asynchronous on s; no allocation. */
+rr_status rr_build_isw_field(rr_tensor t, const rr_field_desc* phi_curr,
+                             const rr_field_desc* phi_prev, double inv_dt, rr_stream s);
 
 /* Cell-centre tidal tensor (Eq. tidalexample, the cell's own level) for the
  * nearest-grid-point integral (Eq. Iclensing_ngp): uniform tensors then hold

@@ -16,11 +16,11 @@ STATUS_NAMES = {0: "RR_OK", -1: "RR_ERR_INVALID_ARG", -2: "RR_ERR_UNSUPPORTED", 
                 -4: "RR_ERR_HIP", -5: "RR_ERR_OCTREE", -6: "RR_ERR_DOMAIN",
                 -7: "RR_ERR_NONFINITE", -8: "RR_ERR_CAPACITY"}
 GRID_UNIFORM, GRID_OCTREE = 0, 1
-FIELD_PHI, FIELD_DELTA = 0, 1
+FIELD_PHI, FIELD_DELTA, FIELD_PHI_DOT = 0, 1, 2
 BOUNDARY_PERIODIC, BOUNDARY_OPEN = 0, 1
 PREC_FP64, PREC_FP32_KAHAN = 0, 1
 F32, F64 = 0, 1
-Q_KAPPA, Q_GAMMA1, Q_GAMMA2 = 0, 1, 2
+Q_KAPPA, Q_GAMMA1, Q_GAMMA2, Q_SCALAR = 0, 1, 2, 3
 INTEGRAL_TRILINEAR, INTEGRAL_NGP = 0, 1
 RAY_OK, RAY_OUT_OF_DOMAIN, RAY_MAX_STEPS, RAY_NONFINITE = 0, 1, 2, 3
 
@@ -55,6 +55,8 @@ SIGNATURES = [
     ("rr_build_tidal_tensor_centres", _i32, [_vp, C.POINTER(FieldDesc), _vp]),
     ("rr_build_method_a_fields", _i32, [_vp, C.POINTER(FieldDesc), C.POINTER(FieldDesc),
                                         C.c_double, _vp]),
+    ("rr_build_isw_field", _i32, [_vp, C.POINTER(FieldDesc), C.POINTER(FieldDesc), C.c_double,
+                                  _vp]),
     ("rr_build_tidal_tensor_box", _i32, [_vp, C.POINTER(FieldDesc), C.POINTER(_i32),
                                          C.POINTER(_i32), _vp]),
     ("rr_tensor_layout", _i32, [_vp, C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_i32),

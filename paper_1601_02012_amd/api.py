@@ -17,7 +17,8 @@ from . import _abi as A
 from ._abi import RRError  # noqa: F401  (re-export)
 
 PREC = {"fp64": A.PREC_FP64, "fp32": A.PREC_FP32_KAHAN, "fp32_kahan": A.PREC_FP32_KAHAN}
-QUANTITY = {"kappa": A.Q_KAPPA, "gamma1": A.Q_GAMMA1, "gamma2": A.Q_GAMMA2}
+QUANTITY = {"kappa": A.Q_KAPPA, "gamma1": A.Q_GAMMA1, "gamma2": A.Q_GAMMA2,
+            "scalar": A.Q_SCALAR}
 
 _lib = A.lib()   # fail loudly at import if the HIP library is missing
 
@@ -64,9 +65,11 @@ class Grid:
             self.n = int(values.shape[0]) if n_base is None else int(n_base)
         self.boundary = A.BOUNDARY_OPEN if boundary == "open" else A.BOUNDARY_PERIODIC
         self.max_level = int(max_level)
-        if field not in ("phi", "delta"):
-            raise ValueError("field is 'phi' (potential) or 'delta' (density contrast)")
-        self.field = A.FIELD_DELTA if field == "delta" else A.FIELD_PHI
+        fields = {"phi": A.FIELD_PHI, "delta": A.FIELD_DELTA, "phi_dot": A.FIELD_PHI_DOT}
+        if field not in fields:
+            raise ValueError("field is 'phi' (potential), 'delta' (density contrast) or "
+                             "'phi_dot' (the potential's rate of change, ISW)")
+        self.field = fields[field]
 
     def desc(self) -> A.FieldDesc:
         d = A.FieldDesc()
@@ -110,6 +113,17 @@ class TidalTensor:
         A.check("rr_build_method_a_fields",
                 _lib.rr_build_method_a_fields(self.handle, C.byref(dd), C.byref(dp),
                                               float(delta_coeff), _stream(stream)))
+        return self
+
+    def build_isw(self, phi_curr: Grid, phi_prev: Grid, inv_dt: float,
+                  stream=None) -> "TidalTensor":
+        """rr_build_isw_field: vertex values of (phi_curr - phi_prev) * inv_dt for a
+        tensor created from a 'phi_dot' grid (ISW integrand, trace with
+        quantity="scalar")."""
+        dc, dp = phi_curr.desc(), phi_prev.desc()
+        A.check("rr_build_isw_field",
+                _lib.rr_build_isw_field(self.handle, C.byref(dc), C.byref(dp), float(inv_dt),
+                                        _stream(stream)))
         return self
 
     def build_centres(self, grid: Optional[Grid] = None, stream=None) -> "TidalTensor":

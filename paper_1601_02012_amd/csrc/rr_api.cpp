@@ -56,6 +56,7 @@ struct rr_tensor_s {
   int32_t content = 0;         // uniform records: 0 unbuilt, 1 vertex tensors, 2 cell centres,
                                // 3 Method A vertex fields
   int32_t method_a = 0;        // created from a density field: (c delta, grad Phi) records
+  int32_t isw = 0;             // created from a rate field: one scalar per vertex
   std::unique_ptr<rr::OctreeTensor> oct;
 };
 
@@ -111,10 +112,12 @@ rr_status validate_field(const rr_field_desc* f) {
   if (!f) return fail(RR_ERR_INVALID_ARG, "field descriptor is NULL");
   if (f->kind != RR_GRID_UNIFORM && f->kind != RR_GRID_OCTREE)
     return fail(RR_ERR_INVALID_ARG, "unknown grid kind %d", f->kind);
-  if (f->field != RR_FIELD_PHI && f->field != RR_FIELD_DELTA)
+  if (f->field != RR_FIELD_PHI && f->field != RR_FIELD_DELTA && f->field != RR_FIELD_PHI_DOT)
     return fail(RR_ERR_INVALID_ARG, "unknown field kind %d", f->field);
   if (f->field == RR_FIELD_DELTA && f->kind != RR_GRID_UNIFORM)
     return fail(RR_ERR_UNSUPPORTED, "Method A (density fields) is implemented for uniform grids");
+  if (f->field == RR_FIELD_PHI_DOT && f->kind != RR_GRID_UNIFORM)
+    return fail(RR_ERR_UNSUPPORTED, "the ISW integrand is implemented for uniform grids");
   if (f->dtype != RR_F32 && f->dtype != RR_F64)
     return fail(RR_ERR_INVALID_ARG, "unknown dtype %d", f->dtype);
   if (f->boundary != RR_BOUNDARY_PERIODIC && f->boundary != RR_BOUNDARY_OPEN)
@@ -165,7 +168,8 @@ rr_status rr_tensor_create(const rr_field_desc* f, rr_precision p, rr_tensor* ou
   if (f->kind == RR_GRID_UNIFORM) {
     const int64_t nv = (int64_t)f->n_base * f->n_base * f->n_base;
     t->method_a = f->field == RR_FIELD_DELTA;
-    t->record_bytes = (t->method_a ? 4 : 6) * (p == RR_PREC_FP32_KAHAN ? 4 : 8);
+    t->isw = f->field == RR_FIELD_PHI_DOT;
+    t->record_bytes = (t->method_a ? 4 : (t->isw ? 1 : 6)) * (p == RR_PREC_FP32_KAHAN ? 4 : 8);
     t->n_records = nv;
     hipError_t e = hipMalloc(&t->data, (size_t)nv * t->record_bytes);
     if (e != hipSuccess) return fail(RR_ERR_OOM, "vertex tensor: %s", hipGetErrorString(e));
@@ -201,9 +205,9 @@ rr_status rr_tensor_layout(rr_tensor t, const void** data, int64_t* n_records,
 
 rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s) {
   if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
-  if (t->method_a || (f && f->field != RR_FIELD_PHI))
+  if (t->method_a || t->isw || (f && f->field != RR_FIELD_PHI))
     return fail(RR_ERR_INVALID_ARG, "tidal tensors are built from potentials (Method A: "
-                                    "rr_build_method_a_fields)");
+                                    "rr_build_method_a_fields; ISW: rr_build_isw_field)");
   rr_status st = validate_field(f);
   if (st != RR_OK) return st;
   if (f->kind != t->kind || f->n_base != t->n || f->boundary != t->boundary)
@@ -226,7 +230,7 @@ rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s
 rr_status rr_build_tidal_tensor_box(rr_tensor t, const rr_field_desc* f, const int32_t lo[3],
                                      const int32_t size[3], rr_stream s) {
   if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
-  if (t->method_a || (f && f->field != RR_FIELD_PHI))
+  if (t->method_a || t->isw || (f && f->field != RR_FIELD_PHI))
     return fail(RR_ERR_INVALID_ARG, "tidal tensors are built from potentials");
   if (!lo || !size) return fail(RR_ERR_INVALID_ARG, "box pointers are NULL");
   rr_status st = validate_field(f);
@@ -256,7 +260,7 @@ rr_status rr_build_tidal_tensor_box(rr_tensor t, const rr_field_desc* f, const i
 
 rr_status rr_build_tidal_tensor_centres(rr_tensor t, const rr_field_desc* f, rr_stream s) {
   if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
-  if (t->method_a || (f && f->field != RR_FIELD_PHI))
+  if (t->method_a || t->isw || (f && f->field != RR_FIELD_PHI))
     return fail(RR_ERR_INVALID_ARG, "tidal tensors are built from potentials");
   rr_status st = validate_field(f);
   if (st != RR_OK) return st;
@@ -268,6 +272,31 @@ rr_status rr_build_tidal_tensor_centres(rr_tensor t, const rr_field_desc* f, rr_
                                           (hipStream_t)s),
          "centre tensor launch");
   t->content = 2;
+  return RR_OK;
+}
+
+rr_status rr_build_isw_field(rr_tensor t, const rr_field_desc* phi_curr,
+                             const rr_field_desc* phi_prev, double inv_dt, rr_stream s) {
+  if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
+  if (!t->isw)
+    return fail(RR_ERR_INVALID_ARG, "the tensor was not created for the ISW integrand "
+                                    "(field RR_FIELD_PHI_DOT)");
+  for (const rr_field_desc* f : {phi_curr, phi_prev}) {
+    rr_status st = validate_field(f);
+    if (st != RR_OK) return st;
+    if (f->field != RR_FIELD_PHI) return fail(RR_ERR_INVALID_ARG, "need two potentials");
+    if (f->kind != RR_GRID_UNIFORM || f->n_base != t->n || f->boundary != t->boundary ||
+        f->box_size != t->box)
+      return fail(RR_ERR_INVALID_ARG, "field does not match the grid the tensor was created for");
+  }
+  if (phi_curr->dtype != phi_prev->dtype)
+    return fail(RR_ERR_INVALID_ARG, "the two potentials must share a dtype");
+  if (!std::isfinite(inv_dt)) return fail(RR_ERR_NONFINITE, "inv_dt is not finite");
+  RR_HIP(rr::launch_isw_vertex_field(t->precision, phi_curr->dtype, t->n,
+                                     t->boundary == RR_BOUNDARY_OPEN, phi_curr->values,
+                                     phi_prev->values, inv_dt, t->data, (hipStream_t)s),
+         "ISW field launch");
+  t->content = 4;
   return RR_OK;
 }
 
@@ -343,11 +372,19 @@ rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle
   if (tp->precision != t->precision)
     return fail(RR_ERR_INVALID_ARG, "trace precision %d differs from the tensor's %d",
                 tp->precision, t->precision);
-  if (tp->quantity < RR_Q_KAPPA || tp->quantity > RR_Q_GAMMA2)
+  if (tp->quantity < RR_Q_KAPPA || tp->quantity > RR_Q_SCALAR)
     return fail(RR_ERR_INVALID_ARG, "unknown quantity %d", tp->quantity);
   if (tp->integral != RR_INTEGRAL_TRILINEAR && tp->integral != RR_INTEGRAL_NGP)
     return fail(RR_ERR_INVALID_ARG, "unknown integral %d", tp->integral);
-  if (t->method_a) {
+  if (t->isw) {
+    if (tp->quantity != RR_Q_SCALAR || tp->integral != RR_INTEGRAL_TRILINEAR)
+      return fail(RR_ERR_INVALID_ARG,
+                  "an ISW tensor is traced with RR_Q_SCALAR and the trilinear integral");
+    if (t->content != 0 && t->content != 4)
+      return fail(RR_ERR_INVALID_ARG, "the ISW tensor holds no ISW field");
+  } else if (tp->quantity == RR_Q_SCALAR) {
+    return fail(RR_ERR_INVALID_ARG, "RR_Q_SCALAR needs an ISW tensor (rr_build_isw_field)");
+  } else if (t->method_a) {
     if (tp->quantity != RR_Q_KAPPA || tp->integral != RR_INTEGRAL_TRILINEAR)
       return fail(RR_ERR_UNSUPPORTED, "Method A gives kappa with the trilinear integral only");
   } else if (t->kind == RR_GRID_UNIFORM && t->content != 0 &&
@@ -555,7 +592,7 @@ rr_status rr_trace_rays_sources(rr_plan p, rr_tensor t, const rr_trace_params* t
   for (int32_t i = 0; i < n_bundles; ++i) any_rays |= bundles[i].n_rays > 0;
   if (any_rays && !moments) return fail(RR_ERR_INVALID_ARG, "moments is NULL");
   if (any_rays && !pieces) return fail(RR_ERR_INVALID_ARG, "pieces is NULL");
-  if (t->method_a || tp->integral != RR_INTEGRAL_TRILINEAR)
+  if (t->method_a || t->isw || tp->integral != RR_INTEGRAL_TRILINEAR)
     return fail(RR_ERR_UNSUPPORTED,
                 "the many-source walk integrates the tidal tensor with the trilinear integral");
   const hipStream_t hs = (hipStream_t)s;
@@ -756,6 +793,11 @@ rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const 
   a.quantity = tp->quantity;
   a.integral = tp->integral;
   a.mode = t->method_a ? 2 : (tp->integral == RR_INTEGRAL_NGP ? 1 : 0);
+  if (t->isw) {
+    // int Q dchi~ in base-cell units times h0: the integral in box units
+    a.mode = 4;
+    a.kappa_scale = tp->kappa_scale * h0;
+  }
   if (src) {
     a.mode = 3;
     a.src = src;
@@ -801,7 +843,8 @@ rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
     return fail(RR_ERR_UNSUPPORTED, "the adjoint is implemented for periodic grids only");
   if (t->precision != RR_PREC_FP32_KAHAN || f->dtype != RR_F32)
     return fail(RR_ERR_UNSUPPORTED, "the adjoint takes an FP32 field and an FP32 tensor");
-  if (tp->quantity != RR_Q_KAPPA || tp->integral != RR_INTEGRAL_TRILINEAR || t->method_a)
+  if (tp->quantity != RR_Q_KAPPA || tp->integral != RR_INTEGRAL_TRILINEAR || t->method_a ||
+      t->isw)
     return fail(RR_ERR_UNSUPPORTED,
                 "the adjoint is implemented for Method B kappa with the trilinear integral");
   if (f->field != RR_FIELD_PHI) return fail(RR_ERR_INVALID_ARG, "the adjoint needs a potential");

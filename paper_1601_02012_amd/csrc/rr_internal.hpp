@@ -31,7 +31,8 @@ struct TraceArgs {
   int32_t quantity;
   int32_t integral;
   int32_t mode;              // integrand: 0 tidal tensor, 1 tidal tensor at centres (NGP),
-                             // 2 Method A, 3 the two source-distance moments
+                             // 2 Method A, 3 the two source-distance moments,
+                             // 4 a vertex scalar with a constant kernel (ISW)
   int64_t max_crossings;
   // outputs
   void* kappa;
@@ -72,6 +73,9 @@ hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int ope
 hipError_t launch_method_a_vertex_fields(int precision, int dtype, int n, int open,
                                          const void* delta, const void* phi, double cdelta,
                                          void* fv, hipStream_t s);
+// ISW vertex scalars: mean over the eight incident cells of (curr - prev) * inv_dt
+hipError_t launch_isw_vertex_field(int precision, int dtype, int n, int open, const void* curr,
+                                   const void* prev, double inv_dt, void* qv, hipStream_t s);
 // cell-centre tensor records (one per cell, same layout as the vertex records)
 hipError_t launch_centre_tensor_uniform(int precision, int dtype, int n, int open,
                                         const void* phi, void* tc, hipStream_t s);

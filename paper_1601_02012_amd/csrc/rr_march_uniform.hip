@@ -50,16 +50,20 @@ __device__ __forceinline__ R project(const R* __restrict__ tv, Off off, const R*
 }
 
 // Integrand modes: the tidal tensor with the trilinear integral, the tidal
-// tensor at cell centres (NGP), Method A's (c delta, grad Phi) fields, and
-// the tidal tensor against the two source-distance moments chi and chi^2.
-constexpr int kTidal = 0, kNgp = 1, kMethodA = 2, kSources = 3;
+// tensor at cell centres (NGP), Method A's (c delta, grad Phi) fields, the
+// tidal tensor against the two source-distance moments chi and chi^2, and a
+// vertex scalar with a constant kernel (ISW).
+constexpr int kTidal = 0, kNgp = 1, kMethodA = 2, kSources = 3, kScalar = 4;
 
-// Corner value(s) of the record at `off`: Q = P : T (tidal modes), or
-// (c delta, n . grad Phi) with P[0..2] = n (Method A).
+// Corner value(s) of the record at `off`: Q = P : T (tidal modes),
+// (c delta, n . grad Phi) with P[0..2] = n (Method A), or the scalar (ISW).
 template <typename R, typename Off, int kMode>
 __device__ __forceinline__ void corner_value(const R* __restrict__ tv, Off off, const R* P, R& q,
                                              R& q2) {
-  if constexpr (kMode == kMethodA) {
+  if constexpr (kMode == kScalar) {
+    q = *reinterpret_cast<const R*>(reinterpret_cast<const char*>(tv) + (uint64_t)off);
+    q2 = (R)0;
+  } else if constexpr (kMode == kMethodA) {
     const char* b = reinterpret_cast<const char*>(tv) + (uint64_t)off;
     R t[4];
     if constexpr (sizeof(R) == 4) {
@@ -152,7 +156,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     return;
   }
   R P[6];
-  if constexpr (kMode == kMethodA) {
+  if constexpr (kMode == kMethodA || kMode == kScalar) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) P[c] = (R)d[c];
   } else {
@@ -163,7 +167,8 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   }
 
   const int n = a.n;
-  constexpr Off kRec = (Off)((kMode == kMethodA ? 4 : 6) * sizeof(R));  // bytes per record
+  constexpr Off kRec =
+      (Off)((kMode == kMethodA ? 4 : (kMode == kScalar ? 1 : 6)) * sizeof(R));  // bytes per record
   const Off stride[3] = {kRec, kRec * (Off)n, kRec * (Off)n * (Off)n};
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
@@ -276,6 +281,8 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
       cell_moments<R>(q, fA, fB, L, (R)chiB, ma, mb);
       ic = ma * scale;
       ic2 = mb * scale;
+    } else if constexpr (kMode == kScalar) {
+      ic = cell_integral_scalar<R>(q, fA, fB, L) * scale;
     } else if constexpr (kMode == kMethodA) {
       // Eq. (kappa2): c delta against g, n . grad Phi against dg/dchi, and the
       // step's surface term -[g n . grad Phi] at its first and last point
@@ -377,14 +384,14 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
       const Off da = k0 ? dX[1] : dX[0];
       const Off db = k0 || k1 ? dX[2] : dX[1];
       const Off w0 = base + dk, w1 = w0 + da;
-      if constexpr (kMode == kMethodA) {
+      if constexpr (kMode == kMethodA || kMode == kScalar) {
         R F[4], G[4];
         corner_value<R, Off, kMode>(tv, w0, P, F[0], G[0]);
         corner_value<R, Off, kMode>(tv, w1, P, F[1], G[1]);
         corner_value<R, Off, kMode>(tv, w0 + db, P, F[2], G[2]);
         corner_value<R, Off, kMode>(tv, w1 + db, P, F[3], G[3]);
         shift_face<R>(q, k0, k1, F[0], F[1], F[2], F[3]);
-        shift_face<R>(q2, k0, k1, G[0], G[1], G[2], G[3]);
+        if constexpr (kMode == kMethodA) shift_face<R>(q2, k0, k1, G[0], G[1], G[2], G[3]);
       } else {
         const R F0 = project<R, Off>(tv, w0, P);
         const R F1 = project<R, Off>(tv, w1, P);
@@ -508,51 +515,6 @@ __global__ __launch_bounds__(256) void kappa_from_pieces_kernel(const R* __restr
   }
 }
 
-// Lattice bounds of the rays' end points (the walk between them stays in the
-// box they span).  One wavefront per tile, reduced across the wavefront
-// before one atomic per bound.
-__global__ __launch_bounds__(256) void ray_bounds_kernel(TraceArgs a, int* out) {
-  const int lane = threadIdx.x & 63;
-  const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) +
-                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (tile >= a.n_tiles) return;
-  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-  const int b = find_bundle(a.bundles, a.n_bundles, tile);
-  const DevBundle& B = a.bundles[b];
-  const int64_t local = tile - B.tile_begin;
-  const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
-  const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) {
-    const int64_t ray = (int64_t)iy * B.nx + ix;
-    const double d[3] = {B.dir[3 * ray + 0], B.dir[3 * ray + 1], B.dir[3 * ray + 2]};
-    const double nrm2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (fabs(nrm2 - 1.0) <= 1e-9) {   // other rays are not traced
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int p0 = (int)floor(fma(B.chi_hi, d[k], a.o[k]));
-        const int p1 = (int)floor(fma(B.chi_lo, d[k], a.o[k]));
-        lo[k] = min(p0, p1);
-        hi[k] = max(p0, p1);
-      }
-    }
-  }
-#pragma unroll
-  for (int sh = 32; sh > 0; sh >>= 1) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = min(lo[k], __shfl_xor(lo[k], sh, 64));
-      hi[k] = max(hi[k], __shfl_xor(hi[k], sh, 64));
-    }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (lo[k] != INT_MAX) atomicMin(out + k, lo[k]);
-      if (hi[k] != INT_MIN) atomicMax(out + 3 + k, hi[k]);
-    }
-  }
-}
-
 template <typename R, bool kDebug, typename Off, int kMode>
 hipError_t launch3(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
                    hipStream_t s) {
@@ -576,7 +538,7 @@ hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block,
                   hipStream_t s) {
   const bool dbg = a.hash || a.log || a.count;
   // 32-bit byte offsets when the whole tensor is below 4 GiB
-  const int words = a.mode == kMethodA ? 4 : 6;
+  const int words = a.mode == kMethodA ? 4 : (a.mode == kScalar ? 1 : 6);
   const bool small = (int64_t)a.n * a.n * a.n * (int64_t)(words * sizeof(R)) < (1ll << 32);
   if (a.mode == kMethodA) {
     if (dbg)
@@ -584,6 +546,13 @@ hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block,
                    : launch3<R, true, uint64_t, kMethodA>(tv, a, persistent, block, grid_waves, s);
     return small ? launch3<R, false, uint32_t, kMethodA>(tv, a, persistent, block, grid_waves, s)
                  : launch3<R, false, uint64_t, kMethodA>(tv, a, persistent, block, grid_waves, s);
+  }
+  if (a.mode == kScalar) {
+    if (dbg)
+      return small ? launch3<R, true, uint32_t, kScalar>(tv, a, persistent, block, grid_waves, s)
+                   : launch3<R, true, uint64_t, kScalar>(tv, a, persistent, block, grid_waves, s);
+    return small ? launch3<R, false, uint32_t, kScalar>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, false, uint64_t, kScalar>(tv, a, persistent, block, grid_waves, s);
   }
   if (a.mode == kSources) {
     if (dbg)
@@ -612,13 +581,6 @@ hipError_t launch_march_uniform(int precision, const void* tv, const TraceArgs& 
                                 int block, int grid_waves, hipStream_t s) {
   if (precision == RR_PREC_FP32_KAHAN) return launch<float>(tv, a, persistent, block, grid_waves, s);
   return launch<double>(tv, a, persistent, block, grid_waves, s);
-}
-
-hipError_t launch_ray_bounds(const TraceArgs& a, int* out, hipStream_t s) {
-  const int64_t blocks = (a.n_tiles + 3) / 4;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(ray_bounds_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, out);
-  return hipGetLastError();
 }
 
 hipError_t launch_kappa_from_pieces(int precision, const void* moments, const double* pieces,

@@ -200,6 +200,28 @@ __device__ __forceinline__ void cell_moments(const R* q, const R* uA, const R* u
   mb = b * L;
 }
 
+// int_{chi_B}^{chi_A} Q dchi of the trilinear field (a constant kernel, the
+// ISW integrand): cubic in chi, so the three-point rule is exact.
+template <typename R>
+__device__ __forceinline__ R cell_integral_scalar(const R* q, const R* uA, const R* uB, R L) {
+  R dq[4];
+  dq[0] = q[1] - q[0];
+  dq[1] = q[3] - q[2];
+  dq[2] = q[5] - q[4];
+  dq[3] = q[7] - q[6];
+  const R du0 = uA[0] - uB[0], du1 = uA[1] - uB[1], du2 = uA[2] - uB[2];
+  const R cs[3] = {(R)GL3::c0, (R)GL3::c1, (R)GL3::c2};
+  const R ws[3] = {(R)GL3::w0, (R)GL3::w1, (R)GL3::w2};
+  R acc = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R c = cs[k];
+    acc = fma(ws[k], trilerp(q, dq, fma(du0, c, uB[0]), fma(du1, c, uB[1]), fma(du2, c, uB[2])),
+              acc);
+  }
+  return acc * L;
+}
+
 // FNV-1a, 64 bit, over the 8 little-endian bytes of w.
 __device__ __forceinline__ uint64_t fnv_word(uint64_t h, uint64_t w) {
 #pragma unroll

@@ -286,6 +286,51 @@ __global__ __launch_bounds__(256) void method_a_vertex_kernel(const In* __restri
   }
 }
 
+// ISW integrand (Sec. VII): vertex value = mean over the eight incident cells
+// of the step's finite-difference rate (curr - prev) * inv_dt.  The
+// potentials of consecutive steps are close, so differences and sum are
+// taken in FP64 and rounded once.  One vertex per thread;
+// open grids leave the vertices on the lower faces (no cell below) NaN.
+template <typename In, typename Acc>
+__global__ __launch_bounds__(256) void isw_vertex_kernel(const In* __restrict__ curr,
+                                                         const In* __restrict__ prev,
+                                                         Acc* __restrict__ qv, int n, int open,
+                                                         double inv_dt) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= nn * n) return;
+  const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / nn);
+  Acc out;
+  if (open && (i < 1 || j < 1 || k < 1)) {
+    out = (Acc)__builtin_nan("");
+  } else {
+    const int X[2] = {i == 0 ? n - 1 : i - 1, i};
+    const int Y[2] = {j == 0 ? n - 1 : j - 1, j};
+    const int Z[2] = {k == 0 ? n - 1 : k - 1, k};
+    double acc = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int64_t e = (int64_t)Z[c] * nn + (int64_t)Y[b] * n + X[a];
+          acc += (double)curr[e] - (double)prev[e];
+        }
+    out = (Acc)(acc * (inv_dt * 0.125));
+  }
+  qv[v] = out;
+}
+
+template <typename In, typename Acc>
+hipError_t launch_isw(int n, int open, const void* curr, const void* prev, double inv_dt,
+                      void* qv, hipStream_t s) {
+  const int64_t blocks = ((int64_t)n * n * n + 255) / 256;
+  hipLaunchKernelGGL((isw_vertex_kernel<In, Acc>), dim3((unsigned)blocks), dim3(256), 0, s,
+                     (const In*)curr, (const In*)prev, (Acc*)qv, n, open, inv_dt);
+  return hipGetLastError();
+}
+
 template <typename In, typename Acc>
 hipError_t launch_ma(int n, int open, const void* delta, const void* phi, double cdelta, void* fv,
                      hipStream_t s) {
@@ -360,6 +405,16 @@ hipError_t launch_method_a_vertex_fields(int precision, int dtype, int n, int op
   }
   if (dtype == RR_F32) return launch_ma<float, double>(n, open, delta, phi, cdelta, fv, s);
   return launch_ma<double, double>(n, open, delta, phi, cdelta, fv, s);
+}
+
+hipError_t launch_isw_vertex_field(int precision, int dtype, int n, int open, const void* curr,
+                                   const void* prev, double inv_dt, void* qv, hipStream_t s) {
+  if (precision == RR_PREC_FP32_KAHAN) {
+    if (dtype == RR_F32) return launch_isw<float, float>(n, open, curr, prev, inv_dt, qv, s);
+    return launch_isw<double, float>(n, open, curr, prev, inv_dt, qv, s);
+  }
+  if (dtype == RR_F32) return launch_isw<float, double>(n, open, curr, prev, inv_dt, qv, s);
+  return launch_isw<double, double>(n, open, curr, prev, inv_dt, qv, s);
 }
 
 hipError_t launch_centre_tensor_uniform(int precision, int dtype, int n, int open,

@@ -59,6 +59,8 @@ def test_host_validation_without_gpu(abi):
     d.n_base = 64
     d.field, d.kind = 1, 1
     assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -2      # Method A on an octree
+    d.field, d.kind = 2, 1
+    assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -2      # ISW on an octree
     d.field, d.kind = 5, 0
     assert lib.rr_tensor_create(C.byref(d), 1, C.byref(h)) == -1      # unknown field kind
     d.field = 0
@@ -82,4 +84,5 @@ def test_host_validation_without_gpu(abi):
                                      None) == -1
     assert lib.rr_kappa_from_pieces(None, None, src, 2, 1, None, None, None, None) == -1
     assert "plan" in abi.last_error()
+    assert lib.rr_build_isw_field(None, None, None, 1.0, None) == -1
     assert lib.rr_version() >= 10000
