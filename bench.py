@@ -163,6 +163,8 @@ def lightcone_leg(args, api, I, torch, dev):
     if not args.no_sources:
         results["sources"] = sources_leg(args, api, I, torch, dev, grids, segs, bundles, obs,
                                          results)
+    if not args.no_isw:
+        results["isw"] = isw_leg(args, api, I, torch, dev, grids, segs, bundles, obs)
     del delta0
     if args.copy_probe_mib:
         nb = args.copy_probe_mib * (1 << 20)
@@ -225,6 +227,57 @@ def method_a_leg(args, api, I, torch, dev, delta0, grids, segs, bundles, obs, re
                 "rms_diff_over_rms_kappa": float(np.sqrt(np.mean((ka - kb) ** 2))
                                                  / np.sqrt(np.mean(kb ** 2))),
                 "correlation": float(np.corrcoef(ka, kb)[0, 1])}}
+
+
+def isw_leg(args, api, I, torch, dev, grids, segs, bundles, obs):
+    """The light cone with the ISW integrand (Sec. VII): per segment the vertex
+    field of (Phi_k - Phi_k-1)/dt and the march with a constant kernel
+    2 a_k / c, giving the ISW temperature shift of every ray."""
+    steps = I.isw_steps(len(segs))
+    box = grids[0].box
+    nr = bundles[0][0].n_rays
+    # the potential one step before the first segment
+    prev0 = api.Grid((grids[0].values * float(steps[0][0] / steps[0][1])).contiguous(), box)
+    gd = api.Grid(grids[0].values, box, field="phi_dot")
+    t = api.TidalTensor(gd, "fp32")
+    plan = api.Plan()
+    out = torch.zeros(nr, dtype=torch.float32, device=dev)
+    comp = torch.zeros(nr, dtype=torch.float32, device=dev)
+    st = torch.zeros(nr, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in segs]
+    cross = 0
+    for k in range(len(segs)):
+        t.build_isw(grids[k], grids[k - 1] if k else prev0, steps[k][2])
+        cross += int(api.trace(plan, t, bundles[k], obs, quantity="scalar", debug=True,
+                               persistent=0).count.sum().item())
+
+    def step():
+        out.zero_()
+        comp.zero_()
+        for k in range(len(segs)):
+            ev[k][0].record(stream)
+            t.build_isw(grids[k], grids[k - 1] if k else prev0, steps[k][2])
+            ev[k][1].record(stream)
+            api.trace(plan, t, bundles[k], obs, kappa=out, kappa_comp=comp, status=st,
+                      quantity="scalar", kappa_scale=steps[k][3], persistent=0)
+            ev[k][2].record(stream)
+
+    ms = timed(step, args.steps, args.warmup, "light cone fp32 ISW")
+    build_ms = sum(e[0].elapsed_time(e[1]) for e in ev)
+    march_ms = sum(e[1].elapsed_time(e[2]) for e in ev)
+    m = out.double().cpu().numpy()
+    t.close()
+    del out, comp, prev0
+    torch.cuda.empty_cache()
+    return {"workload": "the light cone with the ISW integrand: per segment the vertex field "
+                        "of (Phi_k - Phi_k-1)/dt (growth-scaled potentials, dt from cosmic "
+                        "time) and a constant kernel 2 a_k / c, FP32-Kahan",
+            "crossings": cross, "ms_per_step": ms, "crossings_per_s": cross / (ms * 1e-3),
+            "field_build_ms_per_segment": build_ms / len(segs),
+            "march_crossings_per_s": cross / (march_ms * 1e-3),
+            "all_rays_ok": bool((st == 0).all().item()),
+            "map_mean": float(m.mean()), "map_rms": float(m.std())}
 
 
 SOURCE_Z = [1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1]
@@ -461,6 +514,7 @@ def main():
     ap.add_argument("--no-method-a", action="store_true")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the ten-source-redshift light cone")
+    ap.add_argument("--no-isw", action="store_true", help="skip the ISW light cone")
     ap.add_argument("--no-tune", action="store_true", help="skip the AMR leg's autotuning")
     ap.add_argument("--tune-lightcone", action="store_true",
                     help="autotune the light-cone launch shape per segment (default: one "
@@ -478,6 +532,7 @@ def main():
         sys.exit(2)
     if args.profile_steps:
         args.no_fp64 = args.no_cpu = args.no_amr = args.no_method_a = args.no_sources = True
+        args.no_isw = True
 
     import torch
     from paper_1601_02012_amd import api, inputs as I
@@ -538,6 +593,8 @@ def main():
         out["method_a"] = results["method_a"]
     if "sources" in results:
         out["many_sources"] = results["sources"]
+    if "isw" in results:
+        out["isw"] = results["isw"]
     if "fp32_box" in results:
         rb = results["fp32_box"]
         box = {"value": rb["cross"] / (rb["step_ms"] * 1e-3), "unit": "crossings/s",

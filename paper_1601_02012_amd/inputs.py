@@ -251,6 +251,33 @@ def lightcone_segments(n_seg: int = 20, a_src: float = 0.5):
     return out
 
 
+def cosmic_time(a: float) -> float:
+    """Cosmic time at scale factor a in units of 1/H0 (flat LCDM)."""
+    H = lambda aa: math.sqrt(OMEGA_M / aa ** 3 + OMEGA_L)
+    return _integrate(lambda aa: 1.0 / (aa * H(aa)), 1e-8, a, pieces=32, order=24)
+
+
+def isw_steps(n_seg: int = 20, a_src: float = 0.5):
+    """Per light-cone segment of lightcone_segments: (s_prev, s_curr, inv_dt,
+    scale) for the ISW integrand.  The potential of step k is s_k Phi0 at the
+    segment's mid-point a_k; the previous step's sits one step earlier (for
+    the first segment, at a_0 - da); inv_dt = 1 / (t(a_k) - t(a_k-1)) in H0
+    units and scale = 2 a_k / (c/H0) per Mpc/h, so that
+    scale * int (dPhi/dt) dchi = (2/c) int a dPhi/dt dchi, the ISW
+    temperature shift of Phi/c^2 (dimensionless)."""
+    a = np.linspace(a_src, 1.0, n_seg + 1)
+    mids = 0.5 * (a[:-1] + a[1:])
+    da = mids[1] - mids[0] if n_seg > 1 else 1.0 - a_src
+    d1 = growth_D(1.0)
+    s = lambda aa: (growth_D(aa) / aa) / d1
+    out = []
+    for k, am in enumerate(mids):
+        ap = mids[k - 1] if k > 0 else am - da
+        out.append((s(ap), s(am), 1.0 / (cosmic_time(am) - cosmic_time(ap)),
+                    2.0 * am / C_OVER_H0))
+    return out
+
+
 def config2_phi0(n: int = 512, box: float = 1000.0) -> np.ndarray:
     return config2_fields(n, box)[1]
 
