@@ -423,17 +423,19 @@ def amr_leg(args, api, I, torch, dev):
     nr = offset
     cross = int(api.trace(plan, tens, bundles, case.observer, debug=True, persistent=1)
                 .count.sum().item())
+    bshape = None if args.no_tune else plan.autotune(tens, bundles, case.observer)
+    pers = -1 if bshape else 1
     kap = torch.zeros(nr, dtype=torch.float32, device=dev)
     comp = torch.zeros(nr, dtype=torch.float32, device=dev)
     st = torch.zeros(nr, dtype=torch.int32, device=dev)
     gs = torch.cuda.Stream()
     with torch.cuda.stream(gs):
         api.trace(plan, tens, bundles, case.observer, kappa=kap, kappa_comp=comp, status=st,
-                  persistent=1)
+                  persistent=pers)
         gs.synchronize()
         plan.graph_begin()
         api.trace(plan, tens, bundles, case.observer, kappa=kap, kappa_comp=comp, status=st,
-                  persistent=1)
+                  persistent=pers)
         plan.graph_end()
     gs.synchronize()
 
@@ -448,7 +450,9 @@ def amr_leg(args, api, I, torch, dev):
     ms = timed(bstep, args.steps, args.warmup, "batched")
     out["batched"] = {"workload": f"{len(specs)} bundles ({nr} rays, sides 256..2048, z_s "
                                   "0.5..2, FoV 1..10 deg, random centres) through the AMR "
-                                  "octree, one persistent launch in a HIP graph, FP32-Kahan",
+                                  "octree, all bundles in each launch (autotuned shape and "
+                                  "passes) replayed from a HIP graph, FP32-Kahan",
+                      "tuned_shape": bshape,
                       "rays": nr, "crossings": cross, "ms_per_step": ms,
                       "crossings_per_s": cross / (ms * 1e-3),
                       "all_rays_ok": bool((st == 0).all().item())}

@@ -317,16 +317,36 @@ rr_status rr_rays_vertex_box(rr_plan p, rr_tensor t, const rr_trace_params* tp,
 
 /* Tune the launch shape for this bundle set: times one-wavefront-per-tile
  * launches (64- and 256-thread workgroups) and persistent workgroups fed by
- * the device queue (8, 16 or 32 wavefronts per compute unit) on scratch
- * outputs, and remembers the fastest for the bundle set; later rr_trace_rays
- * calls with tp->persistent = -1 and the same bundles use it.  Synchronous;
- * allocates and frees scratch buffers; never called inside a capture. */
+ * the device queue (8, 16 or 32 wavefronts per compute unit), each as one
+ * pass over the chi window or split into 4 or 16 passes, on scratch outputs,
+ * and remembers the fastest for the bundle set; later rr_trace_rays /
+ * rr_trace_rays_sources calls with tp->persistent = -1 and the same bundles
+ * use it.  A split march cuts the bundles' chi range into equal steps: a pass
+ * stops every ray on the first face at or below its boundary and the next
+ * pass resumes on that face, so rays that drift apart in a long march (one
+ * through a refined halo, its neighbours past it) start each pass side by
+ * side again; the pieces and their order do not change, and neither do the
+ * results.  Passes are used only without debug outputs and
+ * max_crossings, and (FP32_KAHAN) with kappa_comp given; the plan keeps one
+ * double per ray for the resume points (allocated on first use, outside
+ * graph capture).  Synchronous; allocates and frees scratch buffers; never
+ * called inside a capture. */
 rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,
                            const rr_bundle* bundles, int32_t n_bundles, rr_stream s);
-/* The shape chosen by rr_plan_autotune for a bundle set (and its time in ms). */
+/* Pin the launch shape that calls with tp->persistent = -1 use for this
+ * bundle set, as rr_plan_autotune would record it: persistent 0 or 1, block
+ * 64 or 256 (one-wavefront-per-tile launches), waves_per_cu 1..32
+ * (persistent launches), passes 1..64 (split march, see rr_plan_autotune).
+ * Host only; replaces an earlier choice for the same bundles. */
+rr_status rr_plan_set_shape(rr_plan p, const rr_bundle* bundles, int32_t n_bundles,
+                            int32_t persistent, int32_t block, int32_t waves_per_cu,
+                            int32_t passes);
+
+/* The shape chosen by rr_plan_autotune for a bundle set (and its time in ms);
+ * passes = 1 for an unsplit march. */
 rr_status rr_plan_tuned_shape(rr_plan p, const rr_bundle* bundles, int32_t n_bundles,
                               int32_t* persistent, int32_t* block, int32_t* waves_per_cu,
-                              float* ms);
+                              int32_t* passes, float* ms);
 
 /* Gradient of L = sum_r w_r kappa_r with respect to the potential values of
  * a uniform periodic FP32 field: ADDS dL/dPhi to dl_dphi (device, n_base^3

@@ -74,8 +74,9 @@ SIGNATURES = [
     ("rr_rays_vertex_box", _i32, [_vp, _vp, C.POINTER(TraceParams), C.POINTER(Bundle), _i32,
                                   C.POINTER(_i32), C.POINTER(_i32), _vp]),
     ("rr_plan_autotune", _i32, [_vp, _vp, C.POINTER(TraceParams), C.POINTER(Bundle), _i32, _vp]),
+    ("rr_plan_set_shape", _i32, [_vp, C.POINTER(Bundle), _i32, _i32, _i32, _i32, _i32]),
     ("rr_plan_tuned_shape", _i32, [_vp, C.POINTER(Bundle), _i32, C.POINTER(_i32), C.POINTER(_i32),
-                                   C.POINTER(_i32), C.POINTER(C.c_float)]),
+                                   C.POINTER(_i32), C.POINTER(_i32), C.POINTER(C.c_float)]),
     ("rr_graph_begin", _i32, [_vp, _vp]),
     ("rr_graph_end", _i32, [_vp, _vp]),
     ("rr_graph_launch", _i32, [_vp, _vp]),

@@ -207,12 +207,20 @@ class Plan:
         arr = _bundle_array(bundles)
         A.check("rr_plan_autotune", _lib.rr_plan_autotune(self.handle, tensor.handle, C.byref(tp),
                                                           arr, len(bundles), _stream(stream)))
-        pers, blk, wpc, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+        pers, blk, wpc, pas, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
         A.check("rr_plan_tuned_shape",
                 _lib.rr_plan_tuned_shape(self.handle, arr, len(bundles), C.byref(pers),
-                                         C.byref(blk), C.byref(wpc), C.byref(ms)))
+                                         C.byref(blk), C.byref(wpc), C.byref(pas), C.byref(ms)))
         return {"persistent": pers.value, "block": blk.value, "waves_per_cu": wpc.value,
-                "ms": ms.value}
+                "passes": pas.value, "ms": ms.value}
+
+    def set_shape(self, bundles, *, persistent=0, block=256, waves_per_cu=16, passes=1):
+        """rr_plan_set_shape: the launch shape calls with persistent=-1 use for
+        these bundles (passes > 1: the march split into resumable passes)."""
+        arr = _bundle_array(bundles)
+        A.check("rr_plan_set_shape",
+                _lib.rr_plan_set_shape(self.handle, arr, len(bundles), int(persistent),
+                                       int(block), int(waves_per_cu), int(passes)))
 
     def vertex_box(self, tensor: "TidalTensor", bundles, observer, stream=None):
         """rr_rays_vertex_box: (lo, size) of the vertices these bundles' rays read."""

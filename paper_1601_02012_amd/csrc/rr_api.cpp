@@ -84,6 +84,7 @@ struct TunedShape {
   int32_t persistent = 0;
   int32_t block = 256;
   int32_t waves_per_cu = 16;
+  int32_t passes = 1;
   float ms = 0.0f;
 };
 
@@ -100,6 +101,8 @@ struct rr_plan_s {
   int device = 0;
   std::vector<TunedShape> tuned;
   std::vector<CachedSources> sources;
+  double* resume = nullptr;   // per ray: where the next pass of a split march starts
+  int64_t resume_cap = 0;
 };
 
 namespace {
@@ -352,6 +355,7 @@ rr_status rr_plan_destroy(rr_plan p) {
     if (c.dev) (void)hipFree(c.dev);
   for (auto& c : p->sources)
     if (c.dev) (void)hipFree(c.dev);
+  if (p->resume) (void)hipFree(p->resume);
   if (p->queue) (void)hipFree(p->queue);
   delete p;
   return RR_OK;
@@ -542,7 +546,8 @@ namespace {
 rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
                        int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
                        hipStream_t hs, int persistent, int block, int waves_per_cu,
-                       const double* src = nullptr, int32_t n_src = 0, double* pieces = nullptr);
+                       const double* src = nullptr, int32_t n_src = 0, double* pieces = nullptr,
+                       int passes = 1);
 
 const TunedShape* find_tuned(rr_plan p, const rr_bundle* b, int32_t nb) {
   for (const auto& x : p->tuned)
@@ -567,16 +572,17 @@ rr_status rr_trace_rays(rr_plan p, rr_tensor t, const rr_trace_params* tp, const
     return fail(RR_ERR_INVALID_ARG, "kappa_comp is only used by FP32_KAHAN");
   const hipStream_t hs = (hipStream_t)s;
   int persistent = tp->persistent < 0 ? p->prefer_persistent : (tp->persistent ? 1 : 0);
-  int block = 256, waves_per_cu = p->waves_per_cu;
+  int block = 256, waves_per_cu = p->waves_per_cu, passes = 1;
   if (tp->persistent < 0) {
     if (const TunedShape* ts = find_tuned(p, bundles, n_bundles)) {
       persistent = ts->persistent;
       block = ts->block;
       waves_per_cu = ts->waves_per_cu;
+      passes = ts->passes;
     }
   }
   return launch_trace(p, t, tp, bundles, n_bundles, kappa, kappa_comp, ray_status, hs, persistent,
-                      block, waves_per_cu);
+                      block, waves_per_cu, nullptr, 0, nullptr, passes);
 }
 
 rr_status rr_trace_rays_sources(rr_plan p, rr_tensor t, const rr_trace_params* tp,
@@ -600,16 +606,17 @@ rr_status rr_trace_rays_sources(rr_plan p, rr_tensor t, const rr_trace_params* t
   st = get_sources(p, t, chi_src, n_src, hs, &src);
   if (st != RR_OK) return st;
   int persistent = tp->persistent < 0 ? p->prefer_persistent : (tp->persistent ? 1 : 0);
-  int block = 256, waves_per_cu = p->waves_per_cu;
+  int block = 256, waves_per_cu = p->waves_per_cu, passes = 1;
   if (tp->persistent < 0) {
     if (const TunedShape* ts = find_tuned(p, bundles, n_bundles)) {
       persistent = ts->persistent;
       block = ts->block;
       waves_per_cu = ts->waves_per_cu;
+      passes = ts->passes;
     }
   }
   return launch_trace(p, t, tp, bundles, n_bundles, moments, nullptr, ray_status, hs, persistent,
-                      block, waves_per_cu, src, n_src, pieces);
+                      block, waves_per_cu, src, n_src, pieces, passes);
 }
 
 rr_status rr_kappa_from_pieces(rr_plan p, rr_tensor t, const double* chi_src, int32_t n_src,
@@ -709,8 +716,10 @@ rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,
   q.crossing_count = nullptr;
   q.crossing_log = nullptr;
   q.log_stride = 0;
-  struct Cand { int persistent, block, waves; };
-  const Cand cands[] = {{0, 256, 0}, {0, 64, 0}, {1, 256, 8}, {1, 256, 16}, {1, 256, 32}};
+  struct Cand { int persistent, block, waves, passes; };
+  const Cand cands[] = {{0, 256, 0, 1},  {0, 64, 0, 1},   {1, 256, 8, 1},  {1, 256, 16, 1},
+                        {1, 256, 32, 1}, {0, 256, 0, 4},  {0, 256, 0, 16}, {0, 64, 0, 16},
+                        {1, 256, 16, 16}};
   hipEvent_t e0, e1;
   RR_HIP(hipEventCreate(&e0), "event");
   RR_HIP(hipEventCreate(&e1), "event");
@@ -722,7 +731,8 @@ rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,
     for (int rep = 0; rep < 2; ++rep) {   // first run also uploads the bundle table
       RR_HIP(hipEventRecord(e0, hs), "event record");
       st = launch_trace(p, t, &q, bundles, n_bundles, kap, (float*)comp, (int32_t*)stat, hs,
-                        c.persistent, c.block, c.waves ? c.waves : p->waves_per_cu);
+                        c.persistent, c.block, c.waves ? c.waves : p->waves_per_cu, nullptr, 0,
+                        nullptr, c.passes);
       if (st != RR_OK) break;
       RR_HIP(hipEventRecord(e1, hs), "event record");
       RR_HIP(hipEventSynchronize(e1), "event sync");
@@ -736,6 +746,7 @@ rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,
       best.persistent = c.persistent;
       best.block = c.block;
       best.waves_per_cu = c.waves ? c.waves : p->waves_per_cu;
+      best.passes = c.passes;
     }
   }
   (void)hipEventDestroy(e0);
@@ -754,15 +765,46 @@ rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,
   return RR_OK;
 }
 
+rr_status rr_plan_set_shape(rr_plan p, const rr_bundle* bundles, int32_t n_bundles,
+                            int32_t persistent, int32_t block, int32_t waves_per_cu,
+                            int32_t passes) {
+  if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
+  if (n_bundles < 0 || (n_bundles > 0 && !bundles))
+    return fail(RR_ERR_INVALID_ARG, "bad bundle array");
+  if (persistent != 0 && persistent != 1)
+    return fail(RR_ERR_INVALID_ARG, "persistent must be 0 or 1");
+  if (block != 64 && block != 256) return fail(RR_ERR_INVALID_ARG, "block must be 64 or 256");
+  if (waves_per_cu < 1 || waves_per_cu > 32)
+    return fail(RR_ERR_INVALID_ARG, "waves_per_cu outside [1, 32]");
+  if (passes < 1 || passes > 64) return fail(RR_ERR_INVALID_ARG, "passes outside [1, 64]");
+  TunedShape ts;
+  ts.key.assign(bundles, bundles + n_bundles);
+  ts.persistent = persistent;
+  ts.block = persistent ? 256 : block;
+  ts.waves_per_cu = waves_per_cu;
+  ts.passes = passes;
+  ts.ms = 0.0f;
+  for (auto& x : p->tuned)
+    if (x.key.size() == ts.key.size() &&
+        (ts.key.empty() ||
+         std::memcmp(x.key.data(), ts.key.data(), sizeof(rr_bundle) * x.key.size()) == 0)) {
+      x = ts;
+      return RR_OK;
+    }
+  p->tuned.push_back(ts);
+  return RR_OK;
+}
+
 rr_status rr_plan_tuned_shape(rr_plan p, const rr_bundle* bundles, int32_t n_bundles,
                               int32_t* persistent, int32_t* block, int32_t* waves_per_cu,
-                              float* ms) {
+                              int32_t* passes, float* ms) {
   if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
   const TunedShape* ts = find_tuned(p, bundles, n_bundles);
   if (!ts) return fail(RR_ERR_INVALID_ARG, "no tuned shape for this bundle set");
   if (persistent) *persistent = ts->persistent;
   if (block) *block = ts->block;
   if (waves_per_cu) *waves_per_cu = ts->waves_per_cu;
+  if (passes) *passes = ts->passes;
   if (ms) *ms = ts->ms;
   return RR_OK;
 }
@@ -774,7 +816,7 @@ namespace {
 rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
                        int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
                        hipStream_t hs, int persistent, int block, int waves_per_cu,
-                       const double* src, int32_t n_src, double* pieces) {
+                       const double* src, int32_t n_src, double* pieces, int passes) {
   rr_status st;
   const CachedTable* tab = nullptr;
   st = get_table(p, t, bundles, n_bundles, persistent, hs, &tab);
@@ -814,12 +856,56 @@ rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const 
   a.log_stride = tp->log_stride;
   a.queue = p->queue;
   const int grid_waves = p->cu_count * waves_per_cu;
-  if (persistent) RR_HIP(rr::launch_queue_reset(p->queue, hs), "queue reset");
-  if (t->kind == RR_GRID_UNIFORM) {
-    RR_HIP(rr::launch_march_uniform(t->precision, t->data, a, persistent, block, grid_waves, hs),
-           "march launch");
-  } else {
-    RR_HIP(t->oct->march(a, persistent, grid_waves, hs), "octree march launch");
+  // A long window can be marched in passes: each pass stops every ray on the
+  // first face at or below the pass's chi boundary and the next pass resumes
+  // on that face (the same pieces in the same order: the results are
+  // unchanged).  Rays that drift apart in a long march (one lane through a
+  // refined halo, its neighbours past it) start each pass side by side again.
+  // Only without debug outputs or a crossing limit, and with the Kahan state
+  // kept in memory between passes.
+  const bool debug = tp->crossing_hash || tp->crossing_count || tp->crossing_log;
+  a.pause_chi = -INFINITY;
+  if (passes > 1 && (debug || tp->max_crossings > 0 ||
+                     (t->precision == RR_PREC_FP32_KAHAN && !kappa_comp && !src)))
+    passes = 1;
+  double chi_top = 0.0, chi_bot = INFINITY;
+  if (passes > 1) {
+    int64_t nr = 0;
+    for (int32_t i = 0; i < n_bundles; ++i) {
+      if (bundles[i].n_rays == 0) continue;
+      nr = std::max<int64_t>(nr, bundles[i].ray_offset + bundles[i].n_rays);
+      chi_top = std::max(chi_top, bundles[i].chi_hi / h0);
+      chi_bot = std::min(chi_bot, bundles[i].chi_lo / h0);
+    }
+    if (nr > p->resume_cap) {
+      if (capturing(hs))
+        return fail(RR_ERR_CAPACITY, "split march not prepared before graph capture: run the "
+                                     "call once first");
+      if (p->resume) (void)hipFree(p->resume);
+      p->resume = nullptr;
+      p->resume_cap = 0;
+      hipError_t e = hipMalloc((void**)&p->resume, sizeof(double) * (size_t)nr);
+      if (e != hipSuccess) return fail(RR_ERR_OOM, "pass state: %s", hipGetErrorString(e));
+      p->resume_cap = nr;
+    }
+    RR_HIP(rr::launch_fill(p->resume, nr, INFINITY, hs), "pass state init");
+    a.resume = p->resume;
+  }
+  for (int pass = 0; pass < passes; ++pass) {
+    // pass boundaries at equal steps in chi over the bundles' windows; every
+    // lane of a wave restarts from the same boundary, so neighbouring rays
+    // stay in step (and share their cells' records) through the window
+    if (passes > 1)
+      a.pause_chi = pass == passes - 1 ? -INFINITY
+                                       : chi_top - (chi_top - chi_bot) * (pass + 1) / passes;
+    if (persistent) RR_HIP(rr::launch_queue_reset(p->queue, hs), "queue reset");
+    if (t->kind == RR_GRID_UNIFORM) {
+      RR_HIP(rr::launch_march_uniform(t->precision, t->data, a, persistent, block, grid_waves,
+                                      hs),
+             "march launch");
+    } else {
+      RR_HIP(t->oct->march(a, persistent, grid_waves, hs), "octree march launch");
+    }
   }
   return RR_OK;
 }

@@ -50,6 +50,11 @@ struct TraceArgs {
   const double* src;
   int32_t n_src;
   double* pieces;
+  // passes (resume != nullptr): per ray the chi where the next pass starts
+  // (+inf: the window's chi_hi; -inf: done); a pass stops a ray on the first
+  // face at or below pause_chi (base-cell units; -inf: run to chi_lo)
+  double* resume;
+  double pause_chi;
 };
 
 // Uniform vertex tensor record: 6 components, FP32 (24 B, three 8-byte
@@ -86,6 +91,8 @@ hipError_t launch_ray_bounds(const TraceArgs& a, int* out, hipStream_t s);
 hipError_t launch_march_uniform(int precision, const void* tv, const TraceArgs& a, int persistent,
                                 int block, int grid_waves, hipStream_t s);
 hipError_t launch_queue_reset(unsigned long long* q, hipStream_t s);
+// p[0..n) = v (a kernel: safe inside a graph capture)
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 // kappa of every source from the moment state and the pieces (mode 3)
 hipError_t launch_kappa_from_pieces(int precision, const void* moments, const double* pieces,
                                     const double* src, int n_src, int64_t n_rays, double* kappa,

@@ -172,6 +172,15 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   const Off stride[3] = {kRec, kRec * (Off)n, kRec * (Off)n * (Off)n};
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
+  // a later pass resumes on the face where the last one stopped
+  bool resumed = false;
+  if (a.resume) {
+    const double r0 = a.resume[out];
+    if (!(r0 > lo)) return;   // done in an earlier pass
+    resumed = r0 < chiA;
+    chiA = resumed ? r0 : chiA;
+    if (chiA <= a.pause_chi) return;   // starts in a later pass
+  }
   double r[3], te[3];
   R absd[3];         // f(chi) = 1 - absd (chi - t_exit)
   int px[3];         // lattice coordinate of the exit plane (unwrapped, replicated box)
@@ -205,7 +214,14 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   }
   R fA[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
+  for (int k = 0; k < 3; ++k) {
+    fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
+    // on the entry face of a resumed cell the coordinate is 0, as when the
+    // march steps across that face without stopping
+    if (resumed && d[k] != 0.0 &&
+        chiA == tplane((double)(d[k] > 0.0 ? px[k] + 1 : px[k] - 1), a.o[k], r[k]))
+      fA[k] = (R)0;
+  }
 
   R q[8], q2[8];  // corner values (q2: Method A's gradient term), c = b0 + 2 b1 + 4 b2
   if constexpr (kMode != kNgp) load_corners<R, Off, kMode>(tv, base, dX, P, q, q2);
@@ -241,6 +257,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   int64_t count = 0;
   int32_t st = RR_RAY_OK;
   const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
+  bool paused = false;
 
   for (;;) {
     if (a.open) {
@@ -254,6 +271,10 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
         st = RR_RAY_OUT_OF_DOMAIN;
         break;
       }
+    }
+    if (chiA <= a.pause_chi) {   // the rest of the window is a later pass's
+      paused = true;
+      break;
     }
     if (count >= maxc) {
       st = RR_RAY_MAX_STEPS;
@@ -287,7 +308,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
       // Eq. (kappa2): c delta against g, n . grad Phi against dg/dchi, and the
       // step's surface term -[g n . grad Phi] at its first and last point
       R s = cell_integral_a<R>(q, q2, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis);
-      const bool first = count == 0, last = chiB == lo;
+      const bool first = count == 0 && !resumed, last = chiB == lo;
       if (first || last) {
         R dq[4];
         dq[0] = q2[1] - q2[0]; dq[1] = q2[3] - q2[2]; dq[2] = q2[5] - q2[4]; dq[3] = q2[7] - q2[6];
@@ -425,6 +446,8 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   } else {
     reinterpret_cast<double*>(a.kappa)[out] = sum;
   }
+  // stopped at the pass boundary: the next pass starts on the face ahead
+  if (a.resume) a.resume[out] = paused ? chiA : -INFINITY;
   if (a.status) a.status[out] = st;
   if constexpr (kDebug) {
     if (a.hash) a.hash[out] = hv;
@@ -484,6 +507,11 @@ __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restr
 }
 
 __global__ void queue_reset_kernel(unsigned long long* q) { *q = 0ull; }
+
+__global__ __launch_bounds__(256) void fill_kernel(double* __restrict__ p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
 
 // kappa of every source (Eqs. Isources, Isources1) once the walk has reached
 // the observer: the moment state holds what lies below the nearest source,
@@ -594,6 +622,13 @@ hipError_t launch_kappa_from_pieces(int precision, const void* moments, const do
   else
     hipLaunchKernelGGL(kappa_from_pieces_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        (const double*)moments, pieces, src, n_src, n_rays, kappa);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -379,6 +379,15 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   const int n = T.n;
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
+  // a later pass resumes on the face where the last one stopped
+  bool resumed = false;
+  if (a.resume) {
+    const double r0 = a.resume[out];
+    if (!(r0 > lo)) return;   // done in an earlier pass
+    resumed = r0 < chiA;
+    chiA = resumed ? r0 : chiA;
+    if (chiA <= a.pause_chi) return;   // starts in a later pass
+  }
   R P[6];
   double r[3];
   int m[3], wb[3];
@@ -441,8 +450,18 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   };
   set_level(l);
   R fA[3];
+  {
+    const double hl = ldexp(1.0, -l);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
+    for (int k = 0; k < 3; ++k) {
+      fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
+      // on the entry face of a resumed leaf the coordinate is 0, as when the
+      // march steps across that face without stopping
+      if (resumed && r[k] != 0.0 &&
+          chiA == tplane((double)(r[k] > 0.0 ? m[k] + 1 : m[k]) * hl, a.o[k], r[k]))
+        fA[k] = (R)0;
+    }
+  }
   R q[8];
   if constexpr (kMode != kOctNgp) load_leaf<R, Off>(cv, cell, flip, P, q);
 
@@ -476,8 +495,13 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   int64_t count = 0;
   int32_t st = RR_RAY_OK;
   const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
+  bool paused = false;
 
   for (;;) {
+    if (chiA <= a.pause_chi) {   // the rest of the window is a later pass's
+      paused = true;
+      break;
+    }
     if (count >= maxc) {
       st = RR_RAY_MAX_STEPS;
       break;
@@ -667,6 +691,8 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   } else {
     reinterpret_cast<double*>(a.kappa)[out] = sum;
   }
+  // stopped at the pass boundary: the next pass starts on the face ahead
+  if (a.resume) a.resume[out] = paused ? chiA : -INFINITY;
   if (a.status) a.status[out] = st;
   if constexpr (kDebug) {
     if (a.hash) a.hash[out] = hv;
