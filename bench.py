@@ -460,6 +460,37 @@ def amr_leg(args, api, I, torch, dev):
     return out
 
 
+def amr_profile(args, api, I, torch, dev):
+    """The AMR map alone, for profilers: one tensor build and two timed marches
+    of all 4096^2 rays with a fixed launch shape (one-wavefront-per-tile,
+    256-thread workgroups) split into --amr-passes passes."""
+    case = I.config3()
+    tr = case.tree
+    grid = api.Grid(torch.as_tensor(case.phi.astype(np.float32), device=dev), case.box,
+                    n_base=tr.n, child_oct=torch.as_tensor(tr.child_oct, device=dev),
+                    max_level=tr.max_level)
+    tens = api.TidalTensor(grid, "fp32").build(grid)
+    plan = api.Plan()
+    b = I.config3_rays(args.amr_rays)
+    gb = [api.RayBundle(torch.as_tensor(b.dirs, device=dev), b.nx, b.ny, b.chi_s, b.chi_hi,
+                        b.chi_lo)]
+    plan.set_shape(gb, persistent=0, block=256, passes=args.amr_passes)
+    nr = b.nx * b.ny
+    kap = torch.zeros(nr, dtype=torch.float32, device=dev)
+    comp = torch.zeros(nr, dtype=torch.float32, device=dev)
+    ms = []
+    for _ in range(2):
+        kap.zero_()
+        comp.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.trace(plan, tens, gb, case.observer, kappa=kap, kappa_comp=comp, persistent=-1)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+        log(f"AMR map, {args.amr_passes} passes: {ms[-1]:.1f} ms")
+    return {"amr_profile": {"passes": args.amr_passes, "ms": ms, "cells": int(tr.n_cells)}}
+
+
 def cpu_baseline(ctx, results, target_s):
     """FP64 oracle on the host over the whole light cone (every segment with
     its own vertex tensor) for a deterministic ray sample."""
@@ -526,6 +557,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", action="store_true",
                     help="short light-cone-only run for profilers (no FP64, CPU or AMR legs)")
+    ap.add_argument("--profile-amr", action="store_true",
+                    help="AMR map only (for profilers): tensor build and two marches")
+    ap.add_argument("--amr-passes", type=int, default=16,
+                    help="passes of the --profile-amr march")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the light cone, copy this many MiB device-to-device (a plain "
                          "copy kernel that calibrates the profiler's byte counters)")
@@ -543,6 +578,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_amr:
+        print(json.dumps(amr_profile(args, api, I, torch, dev)), flush=True)
+        return
     results, ctx = lightcone_leg(args, api, I, torch, dev)
     r32 = results["fp32"]
     nseg = len(ctx["segs"])

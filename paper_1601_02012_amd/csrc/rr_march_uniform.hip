@@ -143,7 +143,7 @@ __device__ __forceinline__ void shift_face(R* q, bool k0, bool k1, R F0, R F1, R
 // wrapped index of the exit vertex layer; the cell's entry corner is one byte
 // offset into the vertex array (32 bit when the tensor is below 4 GiB), with
 // per-axis steps to the exit layer (modular arithmetic).
-template <typename R, bool kDebug, typename Off, int kMode>
+template <typename R, bool kDebug, typename Off, int kMode, bool kPass>
 __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const DevBundle& B,
                           int64_t ray) {
   const int64_t out = B.ray_offset + ray;
@@ -173,13 +173,11 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
   // a later pass resumes on the face where the last one stopped
-  bool resumed = false;
-  if (a.resume) {
+  if constexpr (kPass) {
     const double r0 = a.resume[out];
-    if (!(r0 > lo)) return;   // done in an earlier pass
-    resumed = r0 < chiA;
-    chiA = resumed ? r0 : chiA;
-    if (chiA <= a.pause_chi) return;   // starts in a later pass
+    if (!(r0 > lo)) return;             // done in an earlier pass
+    chiA = fmin(r0, chiA);              // +inf before the first pass
+    if (chiA <= a.pause_chi) return;    // starts in a later pass
   }
   double r[3], te[3];
   R absd[3];         // f(chi) = 1 - absd (chi - t_exit)
@@ -216,9 +214,9 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
-    // on the entry face of a resumed cell the coordinate is 0, as when the
-    // march steps across that face without stopping
-    if (resumed && d[k] != 0.0 &&
+    // on the entry face (a resumed ray, or a window that starts on a face)
+    // the coordinate is 0, as when the march steps across that face
+    if (kPass && d[k] != 0.0 &&
         chiA == tplane((double)(d[k] > 0.0 ? px[k] + 1 : px[k] - 1), a.o[k], r[k]))
       fA[k] = (R)0;
   }
@@ -257,7 +255,6 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   int64_t count = 0;
   int32_t st = RR_RAY_OK;
   const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
-  bool paused = false;
 
   for (;;) {
     if (a.open) {
@@ -272,9 +269,8 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
         break;
       }
     }
-    if (chiA <= a.pause_chi) {   // the rest of the window is a later pass's
-      paused = true;
-      break;
+    if constexpr (kPass) {
+      if (chiA <= a.pause_chi) break;   // the rest of the window is a later pass's
     }
     if (count >= maxc) {
       st = RR_RAY_MAX_STEPS;
@@ -308,7 +304,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
       // Eq. (kappa2): c delta against g, n . grad Phi against dg/dchi, and the
       // step's surface term -[g n . grad Phi] at its first and last point
       R s = cell_integral_a<R>(q, q2, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis);
-      const bool first = count == 0 && !resumed, last = chiB == lo;
+      const bool first = count == 0 && chiA == B.chi_hi, last = chiB == lo;
       if (first || last) {
         R dq[4];
         dq[0] = q2[1] - q2[0]; dq[1] = q2[3] - q2[2]; dq[2] = q2[5] - q2[4]; dq[3] = q2[7] - q2[6];
@@ -368,7 +364,10 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
         src_j = jn < a.n_src ? a.src[jn] : -1.0;
       }
     }
-    if (chiB == lo) break;
+    if (chiB == lo) {
+      chiA = lo;
+      break;
+    }
     // step every axis whose exit plane is at chi_B: the exit layer becomes
     // the entry layer, the next layer along the march the exit layer
 #pragma unroll
@@ -433,6 +432,8 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     }
     chiA = chiB;
   }
+  // a ray that ended without reaching chi_lo or an error stopped at a pass boundary
+  const bool paused = st == RR_RAY_OK && chiA > lo;
   if (!(sum == sum) || sum - sum != (R)0) st = RR_RAY_NONFINITE;
   if constexpr (kMode == kSources) {
     if (!(sum2 == sum2) || sum2 - sum2 != (R)0) st = RR_RAY_NONFINITE;
@@ -447,7 +448,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
     reinterpret_cast<double*>(a.kappa)[out] = sum;
   }
   // stopped at the pass boundary: the next pass starts on the face ahead
-  if (a.resume) a.resume[out] = paused ? chiA : -INFINITY;
+  if constexpr (kPass) a.resume[out] = paused ? chiA : -INFINITY;
   if (a.status) a.status[out] = st;
   if constexpr (kDebug) {
     if (a.hash) a.hash[out] = hv;
@@ -455,7 +456,7 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
   }
 }
 
-template <typename R, bool kDebug, typename Off, int kMode>
+template <typename R, bool kDebug, typename Off, int kMode, bool kPass>
 __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -463,7 +464,7 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Off, kMode>(tv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Off, kMode, kPass>(tv, a, B, (int64_t)iy * B.nx + ix);
 }
 
 // One wavefront per tile.  Workgroups are dealt round-robin to the 8 XCDs;
@@ -471,7 +472,7 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
 // is held to 96 VGPRs (5 wavefronts per SIMD): the march waits on dependent
 // gathers, and the fifth wavefront hides more of that latency than the
 // compiler's unconstrained schedule (100 VGPRs, 4 wavefronts) gains.
-template <typename R, bool kDebug, typename Off, int kMode>
+template <typename R, bool kDebug, typename Off, int kMode, bool kPass>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
 void march_uniform_kernel(const R* __restrict__ tv,
                                                             TraceArgs a) {
@@ -485,12 +486,12 @@ void march_uniform_kernel(const R* __restrict__ tv,
   // the tile is the same for the 64 lanes: keep it (and the bundle) scalar
   const int64_t tile = vblk * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
-  run_tile<R, kDebug, Off, kMode>(tv, a, tile, lane);
+  run_tile<R, kDebug, Off, kMode, kPass>(tv, a, tile, lane);
 }
 
 // Persistent workgroups: every wavefront pulls tiles from a device counter
 // until the queue is drained (every wave reaches the exit test).
-template <typename R, bool kDebug, typename Off, int kMode>
+template <typename R, bool kDebug, typename Off, int kMode, bool kPass>
 __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restrict__ tv,
                                                                 TraceArgs a) {
   const int lane = threadIdx.x & 63;
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restr
     const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
     if (tile >= a.n_tiles) break;
-    run_tile<R, kDebug, Off, kMode>(tv, a, tile, lane);
+    run_tile<R, kDebug, Off, kMode, kPass>(tv, a, tile, lane);
   }
 }
 
@@ -543,64 +544,52 @@ __global__ __launch_bounds__(256) void kappa_from_pieces_kernel(const R* __restr
   }
 }
 
-template <typename R, bool kDebug, typename Off, int kMode>
+template <typename R, bool kDebug, typename Off, int kMode, bool kPass>
 hipError_t launch3(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
                    hipStream_t s) {
   const int wpb = block / 64;
   if (persistent) {
     const int blocks = (grid_waves + wpb - 1) / wpb;
-    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Off, kMode>), dim3(blocks), dim3(block), 0, s,
+    hipLaunchKernelGGL((march_uniform_persistent<R, kDebug, Off, kMode, kPass>), dim3(blocks), dim3(block), 0, s,
                        (const R*)tv, a);
   } else {
     int64_t blocks = (a.n_tiles + wpb - 1) / wpb;
     if (blocks == 0) return hipSuccess;
     blocks = (blocks + 7) / 8 * 8;   // the XCD remap is a bijection on multiples of 8
-    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Off, kMode>), dim3((unsigned)blocks), dim3(block),
+    hipLaunchKernelGGL((march_uniform_kernel<R, kDebug, Off, kMode, kPass>), dim3((unsigned)blocks), dim3(block),
                        0, s, (const R*)tv, a);
   }
   return hipGetLastError();
 }
 
+template <typename R, int kMode>
+hipError_t launch_mode(const void* tv, const TraceArgs& a, bool small, int persistent, int block,
+                       int grid_waves, hipStream_t s) {
+  const bool dbg = a.hash || a.log || a.count;
+  // split marches never carry debug outputs (the host keeps those in one pass)
+  if (a.resume)
+    return small ? launch3<R, false, uint32_t, kMode, true>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, false, uint64_t, kMode, true>(tv, a, persistent, block, grid_waves, s);
+  if (dbg)
+    return small ? launch3<R, true, uint32_t, kMode, false>(tv, a, persistent, block, grid_waves, s)
+                 : launch3<R, true, uint64_t, kMode, false>(tv, a, persistent, block, grid_waves, s);
+  return small ? launch3<R, false, uint32_t, kMode, false>(tv, a, persistent, block, grid_waves, s)
+               : launch3<R, false, uint64_t, kMode, false>(tv, a, persistent, block, grid_waves, s);
+}
+
 template <typename R>
 hipError_t launch(const void* tv, const TraceArgs& a, int persistent, int block, int grid_waves,
                   hipStream_t s) {
-  const bool dbg = a.hash || a.log || a.count;
   // 32-bit byte offsets when the whole tensor is below 4 GiB
   const int words = a.mode == kMethodA ? 4 : (a.mode == kScalar ? 1 : 6);
   const bool small = (int64_t)a.n * a.n * a.n * (int64_t)(words * sizeof(R)) < (1ll << 32);
-  if (a.mode == kMethodA) {
-    if (dbg)
-      return small ? launch3<R, true, uint32_t, kMethodA>(tv, a, persistent, block, grid_waves, s)
-                   : launch3<R, true, uint64_t, kMethodA>(tv, a, persistent, block, grid_waves, s);
-    return small ? launch3<R, false, uint32_t, kMethodA>(tv, a, persistent, block, grid_waves, s)
-                 : launch3<R, false, uint64_t, kMethodA>(tv, a, persistent, block, grid_waves, s);
+  switch (a.mode) {
+    case kNgp: return launch_mode<R, kNgp>(tv, a, small, persistent, block, grid_waves, s);
+    case kMethodA: return launch_mode<R, kMethodA>(tv, a, small, persistent, block, grid_waves, s);
+    case kSources: return launch_mode<R, kSources>(tv, a, small, persistent, block, grid_waves, s);
+    case kScalar: return launch_mode<R, kScalar>(tv, a, small, persistent, block, grid_waves, s);
+    default: return launch_mode<R, kTidal>(tv, a, small, persistent, block, grid_waves, s);
   }
-  if (a.mode == kScalar) {
-    if (dbg)
-      return small ? launch3<R, true, uint32_t, kScalar>(tv, a, persistent, block, grid_waves, s)
-                   : launch3<R, true, uint64_t, kScalar>(tv, a, persistent, block, grid_waves, s);
-    return small ? launch3<R, false, uint32_t, kScalar>(tv, a, persistent, block, grid_waves, s)
-                 : launch3<R, false, uint64_t, kScalar>(tv, a, persistent, block, grid_waves, s);
-  }
-  if (a.mode == kSources) {
-    if (dbg)
-      return small ? launch3<R, true, uint32_t, kSources>(tv, a, persistent, block, grid_waves, s)
-                   : launch3<R, true, uint64_t, kSources>(tv, a, persistent, block, grid_waves, s);
-    return small ? launch3<R, false, uint32_t, kSources>(tv, a, persistent, block, grid_waves, s)
-                 : launch3<R, false, uint64_t, kSources>(tv, a, persistent, block, grid_waves, s);
-  }
-  if (a.mode == kNgp) {
-    if (dbg)
-      return small ? launch3<R, true, uint32_t, kNgp>(tv, a, persistent, block, grid_waves, s)
-                   : launch3<R, true, uint64_t, kNgp>(tv, a, persistent, block, grid_waves, s);
-    return small ? launch3<R, false, uint32_t, kNgp>(tv, a, persistent, block, grid_waves, s)
-                 : launch3<R, false, uint64_t, kNgp>(tv, a, persistent, block, grid_waves, s);
-  }
-  if (dbg)
-    return small ? launch3<R, true, uint32_t, kTidal>(tv, a, persistent, block, grid_waves, s)
-                 : launch3<R, true, uint64_t, kTidal>(tv, a, persistent, block, grid_waves, s);
-  return small ? launch3<R, false, uint32_t, kTidal>(tv, a, persistent, block, grid_waves, s)
-               : launch3<R, false, uint64_t, kTidal>(tv, a, persistent, block, grid_waves, s);
 }
 
 }  // namespace

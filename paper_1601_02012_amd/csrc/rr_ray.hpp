@@ -3,6 +3,12 @@
 // and the debug hash.
 #pragma once
 
+// Multiply-adds are fused only within one expression (explicit fma() calls
+// and a * b + c written together), never across statements: the march is
+// instantiated with and without the pass logic, and both instantiations must
+// round every piece the same way.
+#pragma clang fp contract(on)
+
 #include "rr_internal.hpp"
 
 namespace rr {
