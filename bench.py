@@ -165,6 +165,8 @@ def lightcone_leg(args, api, I, torch, dev):
                                          results)
     if not args.no_isw:
         results["isw"] = isw_leg(args, api, I, torch, dev, grids, segs, bundles, obs)
+    if not args.no_adjoint:
+        results["adjoint"] = adjoint_leg(args, api, I, torch, dev)
     del delta0
     if args.copy_probe_mib:
         nb = args.copy_probe_mib * (1 << 20)
@@ -460,6 +462,64 @@ def amr_leg(args, api, I, torch, dev):
     return out
 
 
+def adjoint_leg(args, api, I, torch, dev):
+    """The adjoint configuration: L = sum(w kappa) over a 1024^2 map through a
+    256^3 FP32 potential; forward (tensor build + march) and backward
+    (rr_trace_rays_adjoint: scatter of the corner weights, transpose of the
+    vertex mean and stencil) timed per step, with the dot-product identity
+    <A^T w, dPhi> = <w, A dPhi> checked on a random dPhi."""
+    case, w = I.config5()
+    b = case.bundles[0]
+    n, box = case.n, case.box
+    g = api.Grid(torch.as_tensor(case.phi, device=dev), box)
+    t = api.TidalTensor(g, "fp32")
+    plan = api.Plan()
+    gb = [api.RayBundle(torch.as_tensor(b.dirs, device=dev), b.nx, b.ny, b.chi_s, b.chi_hi,
+                        b.chi_lo)]
+    wt = torch.as_tensor(w, dtype=torch.float32, device=dev)
+    nr = b.nx * b.ny
+    t.build(g)
+    cross = int(api.trace(plan, t, gb, case.observer, debug=True, persistent=0)
+                .count.sum().item())
+    kap = torch.zeros(nr, dtype=torch.float32, device=dev)
+    comp = torch.zeros(nr, dtype=torch.float32, device=dev)
+    grad = torch.zeros((n, n, n), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step():
+        kap.zero_()
+        comp.zero_()
+        grad.zero_()
+        ev[0].record(stream)
+        t.build(g)
+        api.trace(plan, t, gb, case.observer, kappa=kap, kappa_comp=comp, persistent=0)
+        ev[1].record(stream)
+        api.trace_adjoint(plan, t, g, gb, case.observer, wt, dl_dphi=grad)
+        ev[2].record(stream)
+
+    ms = timed(step, args.steps, args.warmup, "adjoint (forward + backward)")
+    fwd_ms = ev[0].elapsed_time(ev[1])
+    bwd_ms = ev[1].elapsed_time(ev[2])
+    # dot-product identity on a random perturbation (kappa is linear in Phi)
+    rng = np.random.default_rng(12345)
+    dphi = torch.as_tensor(rng.standard_normal((n, n, n)).astype(np.float32) * 1e-5, device=dev)
+    gd = api.Grid(dphi, box)
+    kd = api.trace(plan, t.build(gd), gb, case.observer, persistent=0).kappa.double()
+    lhs = float(torch.dot(wt.double(), kd).item())
+    rhs = float(torch.dot(grad.double().flatten(), dphi.double().flatten()).item())
+    t.close()
+    del grad, kap, comp, dphi
+    torch.cuda.empty_cache()
+    return {"workload": "adjoint: L = sum(w kappa), w ~ N(0,1), 1024x1024 rays over 5x5 deg "
+                        "to chi_s = 256 Mpc/h through a 256^3 FP32 Gaussian potential (box "
+                        "256 Mpc/h); backward through the march, the vertex mean and the "
+                        "stencil to dL/dPhi",
+            "crossings": cross, "ms_per_step": ms, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "backward_crossings_per_s": cross / (bwd_ms * 1e-3),
+            "dot_product_identity_rel_diff": abs(lhs - rhs) / max(abs(lhs), abs(rhs), 1e-300)}
+
+
 def amr_profile(args, api, I, torch, dev):
     """The AMR map alone, for profilers: one tensor build and two timed marches
     of all 4096^2 rays with a fixed launch shape (one-wavefront-per-tile,
@@ -550,6 +610,7 @@ def main():
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the ten-source-redshift light cone")
     ap.add_argument("--no-isw", action="store_true", help="skip the ISW light cone")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint configuration")
     ap.add_argument("--no-tune", action="store_true", help="skip the AMR leg's autotuning")
     ap.add_argument("--tune-lightcone", action="store_true",
                     help="autotune the light-cone launch shape per segment (default: one "
@@ -571,7 +632,7 @@ def main():
         sys.exit(2)
     if args.profile_steps:
         args.no_fp64 = args.no_cpu = args.no_amr = args.no_method_a = args.no_sources = True
-        args.no_isw = True
+        args.no_isw = args.no_adjoint = True
 
     import torch
     from paper_1601_02012_amd import api, inputs as I
@@ -637,6 +698,8 @@ def main():
         out["many_sources"] = results["sources"]
     if "isw" in results:
         out["isw"] = results["isw"]
+    if "adjoint" in results:
+        out["adjoint"] = results["adjoint"]
     if "fp32_box" in results:
         rb = results["fp32_box"]
         box = {"value": rb["cross"] / (rb["step_ms"] * 1e-3), "unit": "crossings/s",

@@ -60,22 +60,63 @@ __device__ __forceinline__ void corner_weights(const float* uA, const float* uB,
   for (int v = 0; v < 8; ++v) om[v] *= s;
 }
 
-__device__ __forceinline__ void flush_corner(float* __restrict__ lam, uint64_t vid, float acc,
-                                             const float* P) {
-  if (acc == 0.0f) return;
-  float* dst = lam + vid * 6;
+// Sum over the 64 lanes (every lane active; the result in every lane).
+__device__ __forceinline__ float wave_sum(float x) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) atomicAdd(dst + c, acc * P[c]);
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
 }
 
-__device__ void scatter_one(const TraceArgs& a, const DevBundle& B, int64_t ray,
-                            const float* __restrict__ wts, float* __restrict__ lam) {
+// Retire one corner of every lane that has weight on it (acc != 0): its six
+// tensor components get acc * P_ab.  The rays of a tile run side by side and
+// every cell is crossed by many rays, so per-lane atomics on one address
+// would serialise: the retiring lanes are grouped by vertex (one group per
+// distinct vertex, usually one or two per wavefront), each group's six sums
+// are reduced across the wavefront and its first lane issues the global
+// atomics.  Called with all 64 lanes active (acc = 0 for lanes that retire
+// nothing, including lanes whose ray has ended).
+__device__ __forceinline__ void flush_corner(float* __restrict__ lam, uint64_t vid, float acc,
+                                             const float* P, int lane) {
+  bool want = acc != 0.0f;
+  unsigned long long m = __ballot(want);
+  while (m != 0ull) {
+    const int leader = __builtin_ctzll(m);
+    const uint64_t lv = (uint64_t)__shfl((long long)vid, leader, 64);
+    const bool mine = want && vid == lv;
+    float sums[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sums[c] = wave_sum(mine ? acc * P[c] : 0.0f);
+    if (lane == leader) {
+      float* dst = lam + lv * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) atomicAdd(dst + c, sums[c]);
+    }
+    want = want && !mine;
+    m = __ballot(want);
+  }
+}
+
+// One 8 x 8 tile of rays, all 64 lanes kept active to the end (lanes without
+// a ray, or whose ray has ended, take part in the wavefront reductions with
+// nothing to add).
+__device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int iy, int lane,
+                             const float* __restrict__ wts, float* __restrict__ lam) {
+  bool alive = ix < B.nx && iy < B.ny;
+  const int64_t ray = alive ? (int64_t)iy * B.nx + ix : 0;
   const int64_t out = B.ray_offset + ray;
-  const float wr = wts[out] * (float)a.kappa_scale;
-  if (wr == 0.0f) return;
-  const double d[3] = {B.dir[3 * ray + 0], B.dir[3 * ray + 1], B.dir[3 * ray + 2]};
-  const double nrm2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-  if (!(fabs(nrm2 - 1.0) <= 1e-9)) return;
+  float wr = 0.0f;
+  double d[3] = {0.0, 0.0, 1.0};
+  if (alive) {
+    wr = wts[out] * (float)a.kappa_scale;
+    const double e0 = B.dir[3 * ray + 0], e1 = B.dir[3 * ray + 1], e2 = B.dir[3 * ray + 2];
+    const double nrm2 = e0 * e0 + e1 * e1 + e2 * e2;
+    alive = wr != 0.0f && fabs(nrm2 - 1.0) <= 1e-9;
+    if (alive) {
+      d[0] = e0;
+      d[1] = e1;
+      d[2] = e2;
+    }
+  }
   double Pd[6];
   projection(RR_Q_KAPPA, d[0], d[1], d[2], Pd);
   float P[6];
@@ -112,30 +153,54 @@ __device__ void scatter_one(const TraceArgs& a, const DevBundle& B, int64_t ray,
 #pragma unroll
   for (int v = 0; v < 8; ++v) acc[v] = 0.0f;
   int64_t count = 0;
+  bool stopped = false;   // ended by max_crossings: its open corners still retire
 
-  for (;;) {
-    if (count >= maxc) break;
+  while (__ballot(alive) != 0ull) {
+    bool stepped[3] = {false, false, false};
+    float uB[3] = {0.0f, 0.0f, 0.0f};
     double chiB = lo;
-    chiB = te[0] > chiB ? te[0] : chiB;
-    chiB = te[1] > chiB ? te[1] : chiB;
-    chiB = te[2] > chiB ? te[2] : chiB;
-    bool stepped[3];
+    int retire = 0;
+    int kk = -1;
+    bool last = false;
+    if (alive) {
+      if (count >= maxc) {
+        alive = false;
+        stopped = true;
+      } else {
+        chiB = te[0] > chiB ? te[0] : chiB;
+        chiB = te[1] > chiB ? te[1] : chiB;
+        chiB = te[2] > chiB ? te[2] : chiB;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
-    float uB[3];
+        for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float face = d[k] > 0.0 ? 0.0f : 1.0f;
-      uB[k] = stepped[k] ? face : (float)fma(chiB, d[k], cpos[k]);
+        for (int k = 0; k < 3; ++k) {
+          const float face = d[k] > 0.0 ? 0.0f : 1.0f;
+          uB[k] = stepped[k] ? face : (float)fma(chiB, d[k], cpos[k]);
+        }
+        float om[8];
+        corner_weights(uA, uB, (float)(chiA - chiB), (float)chiB, (float)(B.chi_s - chiB),
+                       inv_chis, om);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[v] += om[v];
+        ++count;
+        last = chiB == lo;
+        const int nstep = (int)stepped[0] + (int)stepped[1] + (int)stepped[2];
+        // corners that retire: all eight at the end of the ray or after an
+        // edge/vertex crossing; after a single-axis step along k the face the
+        // ray leaves behind (the crossed face is shared with the next cell)
+        retire = 0xff;
+        if (!last && nstep == 1) {
+          kk = stepped[0] ? 0 : (stepped[1] ? 1 : 2);
+          const int bit = 1 << kk;
+          const int keep = d[kk] > 0.0 ? 0 : bit;   // corners on the crossed face
+          retire = 0;
+#pragma unroll
+          for (int v = 0; v < 8; ++v)
+            if ((v & bit) != keep) retire |= 1 << v;
+        }
+      }
     }
-    float om[8];
-    corner_weights(uA, uB, (float)(chiA - chiB), (float)chiB, (float)(B.chi_s - chiB), inv_chis,
-                   om);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) acc[v] += om[v];
-    ++count;
-    const bool last = chiB == lo;
-    const int nstep = (int)stepped[0] + (int)stepped[1] + (int)stepped[2];
+    if (stopped) retire = 0xff;
     // corner ids of the current cell (v = ix + 2 iy + 4 iz)
     uint64_t vid[8];
     {
@@ -145,29 +210,29 @@ __device__ void scatter_one(const TraceArgs& a, const DevBundle& B, int64_t ray,
       vid[3] = zy01 + off1[0]; vid[4] = zy10 + off0[0]; vid[5] = zy10 + off1[0];
       vid[6] = zy11 + off0[0]; vid[7] = zy11 + off1[0];
     }
-    if (last || nstep != 1) {
-      // end of the ray or an edge/vertex crossing: flush every corner
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        flush_corner(lam, vid[v], acc[v], P);
-        acc[v] = 0.0f;
-      }
-      if (last) break;
+    for (int v = 0; v < 8; ++v)
+      flush_corner(lam, vid[v], ((retire >> v) & 1) ? acc[v] : 0.0f, P, lane);
+    if (stopped) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) acc[v] = 0.0f;
+      stopped = false;
+    }
+    if (!alive) continue;
+    if (last) {
+      alive = false;
+      continue;
+    }
+    if (kk < 0) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) acc[v] = 0.0f;
     } else {
-      // single-axis step along k: the face the ray leaves behind retires, the
-      // face it crosses is shared with the next cell
+      // the crossed face becomes the opposite face of the next cell
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        if (!stepped[k]) continue;
+        if (k != kk) continue;
         const int bit = 1 << k;
-        const int keep = d[k] > 0.0 ? 0 : bit;   // corners on the crossed face
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          if ((v & bit) == keep) continue;
-          flush_corner(lam, vid[v], acc[v], P);
-          acc[v] = 0.0f;
-        }
-        // the crossed face becomes the opposite face of the next cell
+        const int keep = d[k] > 0.0 ? 0 : bit;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
           if ((v & bit) != keep) {
@@ -195,17 +260,6 @@ __device__ void scatter_one(const TraceArgs& a, const DevBundle& B, int64_t ray,
     }
     chiA = chiB;
   }
-  // rays stopped by max_crossings still own their open corners
-  if (count >= maxc) {
-    uint64_t vid[8];
-    const uint64_t zy00 = off0[2] + off0[1], zy01 = off0[2] + off1[1];
-    const uint64_t zy10 = off1[2] + off0[1], zy11 = off1[2] + off1[1];
-    vid[0] = zy00 + off0[0]; vid[1] = zy00 + off1[0]; vid[2] = zy01 + off0[0];
-    vid[3] = zy01 + off1[0]; vid[4] = zy10 + off0[0]; vid[5] = zy10 + off1[0];
-    vid[6] = zy11 + off0[0]; vid[7] = zy11 + off1[0];
-#pragma unroll
-    for (int v = 0; v < 8; ++v) flush_corner(lam, vid[v], acc[v], P);
-  }
 }
 
 __global__ __launch_bounds__(256) void scatter_kernel(TraceArgs a, const float* __restrict__ wts,
@@ -214,14 +268,14 @@ __global__ __launch_bounds__(256) void scatter_kernel(TraceArgs a, const float* 
   const int wave = threadIdx.x >> 6;
   const int64_t nblk = gridDim.x, blk = blockIdx.x;
   const int64_t per = (nblk + 7) / 8;
-  const int64_t tile = ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + wave;
+  const int64_t tile = ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) +
+                       __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
   const DevBundle& B = a.bundles[b];
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
-  const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) scatter_one(a, B, (int64_t)iy * B.nx + ix, wts, lam);
+  scatter_tile(a, B, tx * 8 + (lane & 7), ty * 8 + (lane >> 3), lane, wts, lam);
 }
 
 // Transpose stencil: one thread per cell, all inputs from L2 (Lambda is
