@@ -134,3 +134,109 @@ def test_batched_bundles_persistent_and_graph(api, oracle, amr):
                                   b.chi_lo, tc=tc)
         ok, worst = kappa_tolerance_ok(k[b.ray_offset + idx], ref.kappa)
         assert ok, (s_, worst)
+
+
+@pytest.fixture(scope="module")
+def lightcone():
+    """The light cone to z = 1: 512^3 lognormal potential in a 1 Gpc/h box,
+    scaled by s_k for each of the 20 segments, 2048^2 rays over 5x5 deg."""
+    n, box, nray = 512, 1000.0, 2048
+    _, phi0 = I.config2_fields(n, box)
+    fov = math.radians(5.0)
+    dirs = I.fov_directions((0.0, 0.0, 1.0), fov, fov, nray, nray)
+    return n, box, nray, phi0, I.lightcone_segments(20), I.chi_of_z(1.0), dirs
+
+
+def test_lightcone_full_size_sampled_rays(api, oracle, lightcone):
+    """The light cone as it is timed: per segment an FP32 potential, the whole
+    grid's tensor rebuilt, all 2048^2 rays in one one-wavefront-per-tile
+    launch, FP32-Kahan.  Sampled rays (the map's corners, edge midpoints and
+    centre, and 1500 at random) against the FP64 oracle over all 20 segments:
+    every ray finishes, crossing hashes and counts bit-exact per segment (the
+    same rays traced again with crossing hashes), kappa within tolerance."""
+    import torch
+    n, box, nray, phi0, segs, chi_s, dirs = lightcone
+    obs = (0.0, 0.0, 0.0)
+    nr = nray * nray
+    m, h = nray - 1, nray // 2
+    fixed = [0, m, m * nray, m * nray + m, h, h * nray, h * nray + m, m * nray + h,
+             h * nray + h]
+    rng = np.random.default_rng(2048)
+    sel = np.unique(np.concatenate([fixed, rng.choice(nr, size=1500, replace=False)]))
+    sdirs = np.ascontiguousarray(dirs[sel])
+    phi0_d = torch.as_tensor(phi0, device="cuda")
+    dirs_d = torch.as_tensor(dirs, device="cuda")
+    sdirs_d = torch.as_tensor(sdirs, device="cuda")
+    plan = api.Plan()
+    kap = torch.zeros(nr, dtype=torch.float32, device="cuda")
+    comp = torch.zeros(nr, dtype=torch.float32, device="cuda")
+    st = torch.zeros(nr, dtype=torch.int32, device="cuda")
+    t = None
+    ref = np.zeros(len(sel))
+    for k, (hi, lo, s) in enumerate(segs):
+        phi = (phi0_d * s).to(torch.float32).contiguous()
+        g = api.Grid(phi, box)
+        if t is None:
+            t = api.TidalTensor(g, "fp32")
+        t.build(g)
+        api.trace(plan, t, [api.RayBundle(dirs_d, nray, nray, chi_s, hi, lo)], obs, kappa=kap,
+                  kappa_comp=comp, status=st, persistent=0)
+        dbg = api.trace(plan, t, [api.RayBundle(sdirs_d, len(sel), 1, chi_s, hi, lo)], obs,
+                        debug=True, persistent=0)
+        tv = oracle.vertex_tensor(phi.double().cpu().numpy())
+        r = oracle.trace_uniform(n, box, obs, sdirs, chi_s, hi, lo, tv=tv)
+        del tv
+        assert np.all(r.status == oracle.RAY_OK)
+        assert np.array_equal(dbg.count.cpu().numpy(), r.ncross), k
+        assert np.array_equal(hashes_u64(dbg.hash), r.hash), k
+        ref += r.kappa
+        print(f"[lightcone] segment {k}: {int(r.ncross.sum())} sampled crossings", flush=True)
+    torch.cuda.synchronize()
+    assert bool((st == 0).all())
+    ok, worst = kappa_tolerance_ok(kap.double().cpu().numpy()[sel], ref)
+    print(f"[lightcone] worst |err| / tol over {len(sel)} rays: {worst:.3g}", flush=True)
+    assert ok, worst
+    t.close()
+    plan.close()
+
+
+def test_adjoint_full_size_sampled_rays(api, oracle):
+    """The adjoint case (256^3 FP32 potential, 1024^2 rays over 5x5 deg to
+    chi_s = 256) in the timed launch: with dL/dkappa nonzero on 400 sampled
+    rays only, dL/dPhi is those rays' gradient, which the oracle computes ray
+    by ray (every cell within 1e-4 of the gradient's scale); with the full
+    seeded weights the dot-product identity <A^T w, dPhi> = <w, A dPhi> holds
+    on a random dPhi (kappa is linear in Phi)."""
+    import torch
+    case, w = I.config5()
+    b = case.bundles[0]
+    n, box = case.n, case.box
+    nr = b.nx * b.ny
+    g = api.Grid(torch.as_tensor(case.phi, device="cuda"), box)
+    t = api.TidalTensor(g, "fp32").build()
+    plan = api.Plan()
+    gb = [api.RayBundle(torch.as_tensor(b.dirs, device="cuda"), b.nx, b.ny, b.chi_s, b.chi_hi,
+                        b.chi_lo)]
+    rng = np.random.default_rng(55)
+    sel = np.sort(rng.choice(nr, size=400, replace=False))
+    ws = np.zeros(nr, dtype=np.float32)
+    ws[sel] = w[sel].astype(np.float32)
+    got = api.trace_adjoint(plan, t, g, gb, case.observer,
+                            torch.as_tensor(ws, device="cuda")).cpu().numpy()
+    ref = oracle.trace_adjoint_uniform(n, box, case.observer, b.dirs[sel], b.chi_s, b.chi_hi,
+                                       b.chi_lo, ws[sel].astype(np.float64))
+    scale = np.abs(ref).max()
+    assert scale > 0
+    np.testing.assert_allclose(got.reshape(-1), ref.reshape(-1), rtol=0, atol=1e-4 * scale)
+    # the dot-product identity with every ray weighted
+    wt = torch.as_tensor(w.astype(np.float32), device="cuda")
+    grad = api.trace_adjoint(plan, t, g, gb, case.observer, wt).double()
+    dphi = torch.as_tensor(rng.standard_normal((n, n, n)).astype(np.float32) * 1e-5,
+                           device="cuda")
+    kd = api.trace(plan, t.build(api.Grid(dphi, box)), gb, case.observer,
+                   persistent=0).kappa.double()
+    lhs = float(torch.dot(wt.double(), kd).item())
+    rhs = float(torch.sum(grad * dphi.double()).item())
+    assert lhs == pytest.approx(rhs, rel=1e-4)
+    t.close()
+    plan.close()
