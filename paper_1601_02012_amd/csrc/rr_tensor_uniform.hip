@@ -122,23 +122,30 @@ __global__ __launch_bounds__(64 * TY) void vertex_tensor_uniform_kernel(const In
   int slot = 0;
   int gz = (k0 - 2) % n;
   if (gz < 0) gz += n;
-  for (int p = k0 - 2; p <= k_end; ++p, slot ^= 1) {
-    // stage plane p (x fastest, wrapped or zero-padded)
-    Acc* pl = plane[slot];
+  // this thread's part of plane p (x fastest, wrapped or zero-padded), read
+  // one plane ahead: the loads of plane p + 1 are in flight while plane p is
+  // differenced and its vertices stored
+  In pre[kStage];
+  auto fetch = [&](int p, int gzp) {
     const bool zin = p >= 0 && p < n;
-    const In* src = phi + (int64_t)gz * nn;
+    const In* src = phi + (int64_t)gzp * nn;
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
-      if (!sact[u]) continue;
-      Acc v;
-      if (open)
-        v = (sin_[u] && zin) ? (Acc)src[soff[u]] : (Acc)0;
+      if (!sact[u] || (open && !(sin_[u] && zin)))
+        pre[u] = (In)0;
       else
-        v = (Acc)src[soff[u]];
-      pl[threadIdx.x + NT * u] = v;
+        pre[u] = src[soff[u]];
     }
+  };
+  fetch(k0 - 2, gz);
+  for (int p = k0 - 2; p <= k_end; ++p, slot ^= 1) {
+    Acc* pl = plane[slot];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u)
+      if (sact[u]) pl[threadIdx.x + NT * u] = (Acc)pre[u];
     if (++gz == n) gz = 0;
     __syncthreads();
+    if (p < k_end) fetch(p + 1, gz);
     // 4x4 patch: rows y = j-2..j+1, columns x = i-2..i+1
     Acc q[4][4];
 #pragma unroll
