@@ -240,113 +240,6 @@ __global__ __launch_bounds__(256) void centre_tensor_uniform_kernel(const In* __
   store_vertex<false>(tc + c * 6, rec);
 }
 
-// Method A vertex fields (Eq. kappa2): per vertex (c delta, dPhi/dx,
-// dPhi/dy, dPhi/dz), the mean over the eight incident cells of delta and of
-// the central-difference gradient (Phi(i+1) - Phi(i-1)) / 2.  Summed over
-// the two cells i-1, i of an axis the gradient is D f(i) / 2 with
-// D f(i) = (f(i+1) - f(i-1)) + (f(i) - f(i-2)), so d/dx = D_x B_y B_z Phi / 16.
-// One vertex per thread; open grids: NaN where the stencil leaves the grid.
-template <typename In, typename Acc>
-__global__ __launch_bounds__(256) void method_a_vertex_kernel(const In* __restrict__ delta,
-                                                              const In* __restrict__ phi,
-                                                              Acc* __restrict__ fv, int n,
-                                                              int open, double cdelta) {
-  const int64_t nn = (int64_t)n * n;
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= nn * n) return;
-  const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / nn);
-  Acc rec[4];
-  if (open && (i < 2 || j < 2 || k < 2 || i > n - 2 || j > n - 2 || k > n - 2)) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) rec[u] = (Acc)__builtin_nan("");
-  } else {
-    auto w = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
-    const int X[4] = {w(i - 2), w(i - 1), i, w(i + 1)};
-    const int Y[4] = {w(j - 2), w(j - 1), j, w(j + 1)};
-    const int Z[4] = {w(k - 2), w(k - 1), k, w(k + 1)};
-    auto P = [&](int x, int y, int z) -> Acc {
-      return (Acc)phi[(int64_t)Z[z] * nn + (int64_t)Y[y] * n + X[x]];
-    };
-    Acc dsum = 0, gx = 0, gy = 0, gz = 0;
-#pragma unroll
-    for (int b = 1; b <= 2; ++b)
-#pragma unroll
-      for (int c = 1; c <= 2; ++c) {
-        gx += (P(3, b, c) - P(1, b, c)) + (P(2, b, c) - P(0, b, c));
-        gy += (P(b, 3, c) - P(b, 1, c)) + (P(b, 2, c) - P(b, 0, c));
-        gz += (P(b, c, 3) - P(b, c, 1)) + (P(b, c, 2) - P(b, c, 0));
-#pragma unroll
-        for (int a = 1; a <= 2; ++a)
-          dsum += (Acc)delta[(int64_t)Z[c] * nn + (int64_t)Y[b] * n + X[a]];
-      }
-    rec[0] = dsum * (Acc)(cdelta * 0.125);
-    rec[1] = gx * (Acc)0.0625;
-    rec[2] = gy * (Acc)0.0625;
-    rec[3] = gz * (Acc)0.0625;
-  }
-  if constexpr (sizeof(Acc) == 4) {
-    reinterpret_cast<float4*>(fv)[v] = make_float4(rec[0], rec[1], rec[2], rec[3]);
-  } else {
-    double2* d = reinterpret_cast<double2*>(fv) + 2 * v;
-    d[0] = make_double2(rec[0], rec[1]);
-    d[1] = make_double2(rec[2], rec[3]);
-  }
-}
-
-// ISW integrand (Sec. VII): vertex value = mean over the eight incident cells
-// of the step's finite-difference rate (curr - prev) * inv_dt.  The
-// potentials of consecutive steps are close, so differences and sum are
-// taken in FP64 and rounded once.  One vertex per thread;
-// open grids leave the vertices on the lower faces (no cell below) NaN.
-template <typename In, typename Acc>
-__global__ __launch_bounds__(256) void isw_vertex_kernel(const In* __restrict__ curr,
-                                                         const In* __restrict__ prev,
-                                                         Acc* __restrict__ qv, int n, int open,
-                                                         double inv_dt) {
-  const int64_t nn = (int64_t)n * n;
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= nn * n) return;
-  const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / nn);
-  Acc out;
-  if (open && (i < 1 || j < 1 || k < 1)) {
-    out = (Acc)__builtin_nan("");
-  } else {
-    const int X[2] = {i == 0 ? n - 1 : i - 1, i};
-    const int Y[2] = {j == 0 ? n - 1 : j - 1, j};
-    const int Z[2] = {k == 0 ? n - 1 : k - 1, k};
-    double acc = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int64_t e = (int64_t)Z[c] * nn + (int64_t)Y[b] * n + X[a];
-          acc += (double)curr[e] - (double)prev[e];
-        }
-    out = (Acc)(acc * (inv_dt * 0.125));
-  }
-  qv[v] = out;
-}
-
-template <typename In, typename Acc>
-hipError_t launch_isw(int n, int open, const void* curr, const void* prev, double inv_dt,
-                      void* qv, hipStream_t s) {
-  const int64_t blocks = ((int64_t)n * n * n + 255) / 256;
-  hipLaunchKernelGGL((isw_vertex_kernel<In, Acc>), dim3((unsigned)blocks), dim3(256), 0, s,
-                     (const In*)curr, (const In*)prev, (Acc*)qv, n, open, inv_dt);
-  return hipGetLastError();
-}
-
-template <typename In, typename Acc>
-hipError_t launch_ma(int n, int open, const void* delta, const void* phi, double cdelta, void* fv,
-                     hipStream_t s) {
-  const int64_t blocks = ((int64_t)n * n * n + 255) / 256;
-  hipLaunchKernelGGL((method_a_vertex_kernel<In, Acc>), dim3((unsigned)blocks), dim3(256), 0, s,
-                     (const In*)delta, (const In*)phi, (Acc*)fv, n, open, cdelta);
-  return hipGetLastError();
-}
-
 template <typename In, typename Acc>
 hipError_t launch_ct(int n, int open, const void* phi, void* tc, hipStream_t s) {
   const int64_t blocks = ((int64_t)n * n * n + 255) / 256;
@@ -401,27 +294,6 @@ hipError_t launch_vertex_tensor_uniform(int precision, int dtype, int n, int ope
   }
   if (dtype == RR_F32) return launch_vt<float, double>(n, open, lo, size, phi, tv, s);
   return launch_vt<double, double>(n, open, lo, size, phi, tv, s);
-}
-
-hipError_t launch_method_a_vertex_fields(int precision, int dtype, int n, int open,
-                                         const void* delta, const void* phi, double cdelta,
-                                         void* fv, hipStream_t s) {
-  if (precision == RR_PREC_FP32_KAHAN) {
-    if (dtype == RR_F32) return launch_ma<float, float>(n, open, delta, phi, cdelta, fv, s);
-    return launch_ma<double, float>(n, open, delta, phi, cdelta, fv, s);
-  }
-  if (dtype == RR_F32) return launch_ma<float, double>(n, open, delta, phi, cdelta, fv, s);
-  return launch_ma<double, double>(n, open, delta, phi, cdelta, fv, s);
-}
-
-hipError_t launch_isw_vertex_field(int precision, int dtype, int n, int open, const void* curr,
-                                   const void* prev, double inv_dt, void* qv, hipStream_t s) {
-  if (precision == RR_PREC_FP32_KAHAN) {
-    if (dtype == RR_F32) return launch_isw<float, float>(n, open, curr, prev, inv_dt, qv, s);
-    return launch_isw<double, float>(n, open, curr, prev, inv_dt, qv, s);
-  }
-  if (dtype == RR_F32) return launch_isw<float, double>(n, open, curr, prev, inv_dt, qv, s);
-  return launch_isw<double, double>(n, open, curr, prev, inv_dt, qv, s);
 }
 
 hipError_t launch_centre_tensor_uniform(int precision, int dtype, int n, int open,
