@@ -122,9 +122,12 @@ __global__ __launch_bounds__(64 * TY) void vertex_tensor_uniform_kernel(const In
   int slot = 0;
   int gz = (k0 - 2) % n;
   if (gz < 0) gz += n;
-  // this thread's part of plane p (x fastest, wrapped or zero-padded), read
-  // one plane ahead: the loads of plane p + 1 are in flight while plane p is
-  // differenced and its vertices stored
+  // this thread's part of plane p (x fastest, wrapped or zero-padded).  With
+  // FP32 records it is read one plane ahead, so that the loads of plane p + 1
+  // are in flight while plane p is differenced and its vertices stored; with
+  // FP64 records (one workgroup per CU) reading ahead is slower (3.3 against
+  // 2.2 ms for 512^3), and each plane is read when it is staged.
+  constexpr bool kAhead = sizeof(Acc) == 4;
   In pre[kStage];
   auto fetch = [&](int p, int gzp) {
     const bool zin = p >= 0 && p < n;
@@ -137,15 +140,18 @@ __global__ __launch_bounds__(64 * TY) void vertex_tensor_uniform_kernel(const In
         pre[u] = src[soff[u]];
     }
   };
-  fetch(k0 - 2, gz);
+  if constexpr (kAhead) fetch(k0 - 2, gz);
   for (int p = k0 - 2; p <= k_end; ++p, slot ^= 1) {
     Acc* pl = plane[slot];
+    if constexpr (!kAhead) fetch(p, gz);
 #pragma unroll
     for (int u = 0; u < kStage; ++u)
       if (sact[u]) pl[threadIdx.x + NT * u] = (Acc)pre[u];
     if (++gz == n) gz = 0;
     __syncthreads();
-    if (p < k_end) fetch(p + 1, gz);
+    if constexpr (kAhead) {
+      if (p < k_end) fetch(p + 1, gz);
+    }
     // 4x4 patch: rows y = j-2..j+1, columns x = i-2..i+1
     Acc q[4][4];
 #pragma unroll
