@@ -60,11 +60,28 @@ __device__ __forceinline__ void corner_weights(const float* uA, const float* uB,
   for (int v = 0; v < 8; ++v) om[v] *= s;
 }
 
-// Sum over the 64 lanes (every lane active; the result in every lane).
+// x of another lane of the same row of 16, picked by a DPP lane pattern.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_lane(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xf, 0xf, false));
+}
+
+// Sum over the 64 lanes (every lane active), returned as a wavefront-uniform
+// value.  Within each row of 16 lanes: add lane i ^ 1, lane i ^ 2 (quad
+// permutes), then the mirrored lane of the half row (the other quad of eight)
+// and of the row (the other eight); the four row sums are then read out of
+// lanes 0, 16, 32 and 48.  Lane moves, no LDS traffic.
 __device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
+  x += dpp_lane<0xb1>(x);    // quad_perm [1,0,3,2]
+  x += dpp_lane<0x4e>(x);    // quad_perm [2,3,0,1]
+  x += dpp_lane<0x141>(x);   // row_half_mirror
+  x += dpp_lane<0x140>(x);   // row_mirror
+  const int b = __float_as_int(x);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(b, 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(b, 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(b, 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(b, 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
 // Retire one corner of every lane that has weight on it (acc != 0): its six
@@ -81,7 +98,9 @@ __device__ __forceinline__ void flush_corner(float* __restrict__ lam, uint64_t v
   unsigned long long m = __ballot(want);
   while (m != 0ull) {
     const int leader = __builtin_ctzll(m);
-    const uint64_t lv = (uint64_t)__shfl((long long)vid, leader, 64);
+    const uint64_t lv =
+        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(vid >> 32), leader) << 32) |
+        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)vid, leader);
     const bool mine = want && vid == lv;
     float sums[6];
 #pragma unroll
