@@ -297,51 +297,125 @@ __global__ __launch_bounds__(256) void scatter_kernel(TraceArgs a, const float* 
   scatter_tile(a, B, tx * 8 + (lane & 7), ty * 8 + (lane >> 3), lane, wts, lam);
 }
 
-// Transpose stencil: one thread per cell, all inputs from L2 (Lambda is
-// written by the scatter just before and fits the last-level caches for the
-// grids this path targets).
-__device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// Transpose stencil, built like the forward tensor: a workgroup owns a
+// 64 x 16 column of cells and marches 16 cells along z; each step stages one
+// vertex plane of Lambda (six components, with a halo of one vertex below and
+// two above in x and y) in LDS, each thread loading its share of the next
+// plane while the current one is used.  Cell c uses vertices c-1 .. c+2 on
+// each axis (t = 0..3); per plane the thread forms the in-plane parts of the
+// six terms, keeps the raw per-column values of the two z-differenced ones,
+// and combines four planes.
+constexpr int kTX = 64, kTY = 16, kTZ = 16;
 
-__global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ lam,
-                                                        float* __restrict__ dphi, int n) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kTX * kTY) void transpose_kernel(const float* __restrict__ lam,
+                                                              float* __restrict__ dphi, int n,
+                                                              int ntx, int nty) {
+  constexpr int NT = kTX * kTY;
+  constexpr int PX = kTX + 3, PY = kTY + 3;
+  constexpr int PL = PX * PY;
+  constexpr int kN = (PL + NT - 1) / NT;
+  __shared__ float sl[2][6][PL];
+  const int b = blockIdx.x;
+  const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
+  const int i0 = bx * kTX, j0 = by * kTY, k0 = bz * kTZ;
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool mine = i < n && j < n;
   const int64_t nn = (int64_t)n * n;
-  if (c >= nn * n) return;
-  const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / nn);
-  int xs[4], ys[4], zs[4];   // c-1, c, c+1, c+2 (wrapped)
+  const int k_end = min(k0 + kTZ, n);       // cells k0 .. k_end - 1
+
+  int off[kN];
+  bool act[kN];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    xs[t] = wrapn(i - 1 + t, n);
-    ys[t] = wrapn(j - 1 + t, n);
-    zs[t] = wrapn(k - 1 + t, n);
+  for (int u = 0; u < kN; ++u) {
+    const int e = threadIdx.x + NT * u;
+    act[u] = e < PL;
+    int wx = (i0 - 1 + e % PX) % n, wy = (j0 - 1 + e / PX) % n;
+    wx = wx < 0 ? wx + n : wx;
+    wy = wy < 0 ? wy + n : wy;
+    off[u] = wy * n + wx;
   }
-  auto L = [&](int tz, int ty, int tx, int comp) -> float {
-    return lam[(((int64_t)zs[tz] * n + ys[ty]) * n + xs[tx]) * 6 + comp];
+  float2 pre[kN][3];
+  auto fetch = [&](int gz) {
+    const float* src = lam + (int64_t)gz * nn * 6;
+#pragma unroll
+    for (int u = 0; u < kN; ++u)
+      if (act[u]) {
+        const float2* r = reinterpret_cast<const float2*>(src + (int64_t)off[u] * 6);
+        pre[u][0] = r[0];
+        pre[u][1] = r[1];
+        pre[u][2] = r[2];
+      }
   };
-  // S' along one axis with B' on the other two: the cell's vertices are
-  // offsets 1, 2 (t index), the stencil spans t = 0..3
-  float sxx = 0.f, syy = 0.f, szz = 0.f, dxy = 0.f, dxz = 0.f, dyz = 0.f;
+
+  // histories over the planes t = 0..3 (vertex planes p-3 .. p)
+  float AXX[4] = {}, AYY[4] = {}, AXY[4] = {};   // in-plane S'x B'y, B'x S'y, D'x D'y
+  float ZZ[4][4] = {};                           // Lzz at the 2x2 columns
+  float XZ[4][2] = {}, YZ[4][2] = {};            // D'x Lxz on rows j, j+1; D'y Lyz on columns i, i+1
+  int slot = 0;
+  int gz = (k0 - 1) % n;
+  if (gz < 0) gz += n;
+  fetch(gz);
+  for (int p = k0 - 1; p <= k_end + 1; ++p, slot ^= 1) {
 #pragma unroll
-  for (int p = 1; p <= 2; ++p)
+    for (int u = 0; u < kN; ++u)
+      if (act[u]) {
+        const int e = threadIdx.x + NT * u;
+        sl[slot][0][e] = pre[u][0].x; sl[slot][1][e] = pre[u][0].y;
+        sl[slot][2][e] = pre[u][1].x; sl[slot][3][e] = pre[u][1].y;
+        sl[slot][4][e] = pre[u][2].x; sl[slot][5][e] = pre[u][2].y;
+      }
+    if (++gz == n) gz = 0;
+    __syncthreads();
+    if (p < k_end + 1) fetch(gz);
+    auto L = [&](int comp, int ty_, int tx_) { return sl[slot][comp][(ty + ty_) * PX + tx + tx_]; };
+    float axx = 0.f, ayy = 0.f, azz[2][2], xz[2], yz[2];
 #pragma unroll
-    for (int q = 1; q <= 2; ++q) {
-      sxx += (L(p, q, 3, 0) - L(p, q, 2, 0)) - (L(p, q, 1, 0) - L(p, q, 0, 0));
-      syy += (L(p, 3, q, 1) - L(p, 2, q, 1)) - (L(p, 1, q, 1) - L(p, 0, q, 1));
-      szz += (L(3, p, q, 2) - L(2, p, q, 2)) - (L(1, p, q, 2) - L(0, p, q, 2));
+    for (int q = 1; q <= 2; ++q)
+      axx += (L(0, q, 3) - L(0, q, 2)) - (L(0, q, 1) - L(0, q, 0));
+#pragma unroll
+    for (int c = 1; c <= 2; ++c)
+      ayy += (L(1, 3, c) - L(1, 2, c)) - (L(1, 1, c) - L(1, 0, c));
+#pragma unroll
+    for (int q = 1; q <= 2; ++q)
+#pragma unroll
+      for (int c = 1; c <= 2; ++c) azz[q - 1][c - 1] = L(2, q, c);
+    float dx3[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dx3[r] = (L(3, r, 3) - L(3, r, 1)) + (L(3, r, 2) - L(3, r, 0));
+    const float axy = (dx3[3] - dx3[1]) + (dx3[2] - dx3[0]);
+#pragma unroll
+    for (int q = 1; q <= 2; ++q) xz[q - 1] = (L(4, q, 3) - L(4, q, 1)) + (L(4, q, 2) - L(4, q, 0));
+#pragma unroll
+    for (int c = 1; c <= 2; ++c) yz[c - 1] = (L(5, 3, c) - L(5, 1, c)) + (L(5, 2, c) - L(5, 0, c));
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+      AXX[h] = AXX[h + 1]; AYY[h] = AYY[h + 1]; AXY[h] = AXY[h + 1];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ZZ[h][c] = ZZ[h + 1][c];
+      XZ[h][0] = XZ[h + 1][0]; XZ[h][1] = XZ[h + 1][1];
+      YZ[h][0] = YZ[h + 1][0]; YZ[h][1] = YZ[h + 1][1];
     }
-  auto Dx = [&](int tz, int ty, int comp) {
-    return (L(tz, ty, 3, comp) - L(tz, ty, 1, comp)) + (L(tz, ty, 2, comp) - L(tz, ty, 0, comp));
-  };
-  auto Dy = [&](int tz, int tx, int comp) {
-    return (L(tz, 3, tx, comp) - L(tz, 1, tx, comp)) + (L(tz, 2, tx, comp) - L(tz, 0, tx, comp));
-  };
+    AXX[3] = axx; AYY[3] = ayy; AXY[3] = axy;
+    ZZ[3][0] = azz[0][0]; ZZ[3][1] = azz[0][1]; ZZ[3][2] = azz[1][0]; ZZ[3][3] = azz[1][1];
+    XZ[3][0] = xz[0]; XZ[3][1] = xz[1];
+    YZ[3][0] = yz[0]; YZ[3][1] = yz[1];
+    if (p >= k0 + 2 && mine) {
+      // cell k = p - 2: the histories hold vertex planes k-1 .. k+2
+      const int k = p - 2;
+      const float sxx = AXX[1] + AXX[2], syy = AYY[1] + AYY[2], dxy = AXY[1] + AXY[2];
+      float szz = 0.f, dxz = 0.f, dyz = 0.f;
 #pragma unroll
-  for (int p = 1; p <= 2; ++p) {
-    dxy += (Dx(p, 3, 3) - Dx(p, 1, 3)) + (Dx(p, 2, 3) - Dx(p, 0, 3));
-    dxz += (Dx(3, p, 4) - Dx(1, p, 4)) + (Dx(2, p, 4) - Dx(0, p, 4));
-    dyz += (Dy(3, p, 5) - Dy(1, p, 5)) + (Dy(2, p, 5) - Dy(0, p, 5));
+      for (int c = 0; c < 4; ++c) szz += (ZZ[3][c] - ZZ[2][c]) - (ZZ[1][c] - ZZ[0][c]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        dxz += (XZ[3][c] - XZ[1][c]) + (XZ[2][c] - XZ[0][c]);
+        dyz += (YZ[3][c] - YZ[1][c]) + (YZ[2][c] - YZ[0][c]);
+      }
+      float* dst = dphi + (int64_t)k * nn + (int64_t)j * n + i;
+      *dst += (sxx + syy + szz) * 0.125f + (dxy + dxz + dyz) * 0.03125f;
+    }
   }
-  dphi[c] += (sxx + syy + szz) * 0.125f + (dxy + dxz + dyz) * 0.03125f;
 }
 
 }  // namespace
@@ -359,9 +433,10 @@ hipError_t launch_adjoint_uniform(const TraceArgs& a, const float* dl_dkappa, fl
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int64_t tb = (nv + 255) / 256;
-  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)tb), dim3(256), 0, s, (const float*)lam,
-                     dl_dphi, a.n);
+  const int ntx = (a.n + kTX - 1) / kTX, nty = (a.n + kTY - 1) / kTY;
+  const int64_t tb = (int64_t)ntx * nty * ((a.n + kTZ - 1) / kTZ);
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)tb), dim3(kTX * kTY), 0, s,
+                     (const float*)lam, dl_dphi, a.n, ntx, nty);
   return hipGetLastError();
 }
 
