@@ -84,16 +84,38 @@ __device__ __forceinline__ float wave_sum(float x) {
   return (r0 + r1) + (r2 + r3);
 }
 
+// A wavefront's cache of retired vertex sums in LDS, direct-mapped on the low
+// bits of the vertex coordinates: the lanes of a tile drift apart by a step
+// or two, so a vertex is often retired by several groups of lanes a few steps
+// apart; their sums meet in the cache, and a vertex goes to global memory
+// (six FP32 atomics) when its slot is taken by another vertex or the tile
+// ends.  Only group leaders touch it, one at a time.
+struct CacheSlot {
+  uint64_t tag;   // vertex id, or kEmpty
+  float v[6];
+};
+constexpr int kSlots = 256;   // x & 7, y & 7, z & 3
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ void flush_slot(float* __restrict__ lam, const CacheSlot& e) {
+  if (e.tag != kEmpty) {
+    float* dst = lam + e.tag * 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) atomicAdd(dst + c, e.v[c]);
+  }
+}
+
 // Retire one corner of every lane that has weight on it (acc != 0): its six
 // tensor components get acc * P_ab.  The rays of a tile run side by side and
 // every cell is crossed by many rays, so per-lane atomics on one address
 // would serialise: the retiring lanes are grouped by vertex (one group per
 // distinct vertex, usually one or two per wavefront), each group's six sums
-// are reduced across the wavefront and its first lane issues the global
-// atomics.  Called with all 64 lanes active (acc = 0 for lanes that retire
-// nothing, including lanes whose ray has ended).
-__device__ __forceinline__ void flush_corner(float* __restrict__ lam, uint64_t vid, float acc,
-                                             const float* P, int lane) {
+// are reduced across the wavefront and its first lane adds them to the
+// wavefront's cache.  Called with all 64 lanes active (acc = 0 for lanes
+// that retire nothing, including lanes whose ray has ended).
+__device__ __forceinline__ void flush_corner(float* __restrict__ lam, CacheSlot* cache,
+                                             uint64_t vid, int slot, float acc, const float* P,
+                                             int lane) {
   bool want = acc != 0.0f;
   unsigned long long m = __ballot(want);
   while (m != 0ull) {
@@ -101,14 +123,22 @@ __device__ __forceinline__ void flush_corner(float* __restrict__ lam, uint64_t v
     const uint64_t lv =
         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(vid >> 32), leader) << 32) |
         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)vid, leader);
+    const int ls = __builtin_amdgcn_readlane(slot, leader);
     const bool mine = want && vid == lv;
     float sums[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) sums[c] = wave_sum(mine ? acc * P[c] : 0.0f);
     if (lane == leader) {
-      float* dst = lam + lv * 6;
+      CacheSlot& e = cache[ls];
+      if (e.tag == lv) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) atomicAdd(dst + c, sums[c]);
+        for (int c = 0; c < 6; ++c) e.v[c] += sums[c];
+      } else {
+        flush_slot(lam, e);
+        e.tag = lv;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) e.v[c] = sums[c];
+      }
     }
     want = want && !mine;
     m = __ballot(want);
@@ -119,7 +149,9 @@ __device__ __forceinline__ void flush_corner(float* __restrict__ lam, uint64_t v
 // a ray, or whose ray has ended, take part in the wavefront reductions with
 // nothing to add).
 __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int iy, int lane,
-                             const float* __restrict__ wts, float* __restrict__ lam) {
+                             const float* __restrict__ wts, float* __restrict__ lam,
+                             CacheSlot* cache) {
+  for (int e = lane; e < kSlots; e += 64) cache[e].tag = kEmpty;
   bool alive = ix < B.nx && iy < B.ny;
   const int64_t ray = alive ? (int64_t)iy * B.nx + ix : 0;
   const int64_t out = B.ray_offset + ray;
@@ -222,6 +254,16 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
     if (stopped) retire = 0xff;
     // corner ids of the current cell (v = ix + 2 iy + 4 iz)
     uint64_t vid[8];
+    int slot[8];
+    {
+      int cx[2], cy[2], cz[2];
+      cx[0] = w[0]; cx[1] = w[0] + 1 == n ? 0 : w[0] + 1;
+      cy[0] = w[1]; cy[1] = w[1] + 1 == n ? 0 : w[1] + 1;
+      cz[0] = w[2]; cz[1] = w[2] + 1 == n ? 0 : w[2] + 1;
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        slot[v] = (cx[v & 1] & 7) | ((cy[(v >> 1) & 1] & 7) << 3) | ((cz[v >> 2] & 3) << 6);
+    }
     {
       const uint64_t zy00 = off0[2] + off0[1], zy01 = off0[2] + off1[1];
       const uint64_t zy10 = off1[2] + off0[1], zy11 = off1[2] + off1[1];
@@ -231,7 +273,7 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
     }
 #pragma unroll
     for (int v = 0; v < 8; ++v)
-      flush_corner(lam, vid[v], ((retire >> v) & 1) ? acc[v] : 0.0f, P, lane);
+      flush_corner(lam, cache, vid[v], slot[v], ((retire >> v) & 1) ? acc[v] : 0.0f, P, lane);
     if (stopped) {
 #pragma unroll
       for (int v = 0; v < 8; ++v) acc[v] = 0.0f;
@@ -279,10 +321,12 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
     }
     chiA = chiB;
   }
+  for (int e = lane; e < kSlots; e += 64) flush_slot(lam, cache[e]);
 }
 
 __global__ __launch_bounds__(256) void scatter_kernel(TraceArgs a, const float* __restrict__ wts,
                                                       float* __restrict__ lam) {
+  __shared__ CacheSlot cache[4][kSlots];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t nblk = gridDim.x, blk = blockIdx.x;
@@ -294,7 +338,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(TraceArgs a, const float* 
   const DevBundle& B = a.bundles[b];
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
-  scatter_tile(a, B, tx * 8 + (lane & 7), ty * 8 + (lane >> 3), lane, wts, lam);
+  scatter_tile(a, B, tx * 8 + (lane & 7), ty * 8 + (lane >> 3), lane, wts, lam,
+               cache[__builtin_amdgcn_readfirstlane(wave)]);
 }
 
 // Transpose stencil, built like the forward tensor: a workgroup owns a
