@@ -36,13 +36,15 @@ struct Tree {
   int64_t nb;
 };
 
+// Base cell holding level-l coordinates I; every caller passes a cell of the
+// domain or one of its neighbours, so I >> l lies in [-1, n] and wraps with
+// one comparison per side.
 __device__ __forceinline__ int64_t base_of(const Tree& T, int l, const int* I) {
   int b[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    int q = I[a] >> l;          // floor division by 2^l (arithmetic shift)
-    q %= T.n;
-    b[a] = q < 0 ? q + T.n : q;
+    const int q = I[a] >> l;    // floor division by 2^l (arithmetic shift)
+    b[a] = q < 0 ? q + T.n : (q >= T.n ? q - T.n : q);
   }
   return ((int64_t)b[2] * T.n + b[1]) * T.n + b[0];
 }
@@ -177,6 +179,7 @@ __device__ __forceinline__ int octant_leaf(const Tree& T, int lv, const int* V, 
 
 template <typename Acc>
 __global__ __launch_bounds__(256) void corner_kernel(Tree T, const Acc* __restrict__ tc,
+                                                     const uint8_t* __restrict__ nfv_leaf,
                                                      Acc* __restrict__ cv, int l, int64_t begin,
                                                      int64_t end) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -251,7 +254,10 @@ __global__ __launch_bounds__(256) void corner_kernel(Tree T, const Acc* __restri
 #pragma unroll
     for (int comp = 0; comp < 6; ++comp) res[comp] *= (Acc)0.125;
   } else {
-    // boundary vertex: Eqs. (alphac3d), (alphaf3d)
+    // boundary vertex: Eqs. (alphac3d), (alphaf3d).  The tree is 2:1
+    // balanced over faces, edges and corners, so the fine leaves here are one
+    // level below lc and N_fv of each is its count of corners touching a
+    // leaf one level coarser, stored per leaf (coarse_corner_kernel).
     int n_coarse = 0, nfv[8], sum_fv = 0;
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
@@ -260,22 +266,8 @@ __global__ __launch_bounds__(256) void corner_kernel(Tree T, const Acc* __restri
         ++n_coarse;
         continue;
       }
-      int lj, Ij[3];
-      cell_coords(T, leaf[o], lj, Ij);
-      int cntv = 0;
-      for (int w = 0; w < 8; ++w) {
-        const int W[3] = {Ij[0] + (w & 1), Ij[1] + ((w >> 1) & 1), Ij[2] + ((w >> 2) & 1)};
-        bool touch = false;
-        for (int o2 = 0; o2 < 8 && !touch; ++o2) {
-          const int J[3] = {W[0] - 1 + (o2 & 1), W[1] - 1 + ((o2 >> 1) & 1),
-                            W[2] - 1 + ((o2 >> 2) & 1)};
-          int64_t cc;
-          touch = descend(T, lj, J, cc) == lc;
-        }
-        cntv += touch;
-      }
-      nfv[o] = cntv;
-      sum_fv += cntv;
+      nfv[o] = nfv_leaf[leaf[o]];
+      sum_fv += nfv[o];
     }
     const Acc ac = (Acc)1 / ((Acc)n_coarse + (Acc)0.125 * (Acc)sum_fv);
 #pragma unroll
@@ -287,6 +279,42 @@ __global__ __launch_bounds__(256) void corner_kernel(Tree T, const Acc* __restri
   }
 #pragma unroll
   for (int comp = 0; comp < 6; ++comp) out[comp] = res[comp];
+}
+
+// Per leaf of level l >= 1: how many of its eight corners touch a leaf of
+// level l - 1 (N_fv of Eqs. alphac3d / alphaf3d).  A corner W touches one when
+// one of the eight level-l cells around it does not exist (the region is
+// covered by a coarser leaf); those cells all lie in the 3 x 3 x 3 block of
+// level-l cells around the leaf, looked up once each.
+__global__ __launch_bounds__(256) void coarse_corner_kernel(Tree T, uint8_t* __restrict__ out,
+                                                            int l, int64_t begin, int64_t end) {
+  const int64_t c = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= end) return;
+  if (T.child[c] >= 0) {
+    out[c] = 0;
+    return;
+  }
+  int lev, I[3];
+  cell_coords(T, c, lev, I);
+  uint32_t coarse = 0;   // bit (dx+1) + 3 (dy+1) + 9 (dz+1)
+  for (int d = 0; d < 27; ++d) {
+    const int J[3] = {I[0] + d % 3 - 1, I[1] + (d / 3) % 3 - 1, I[2] + d / 9 - 1};
+    int64_t cc;
+    if (descend(T, l, J, cc) == l - 1) coarse |= 1u << d;
+  }
+  int cnt = 0;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    bool touch = false;
+#pragma unroll
+    for (int o2 = 0; o2 < 8; ++o2) {
+      const int d = ((w & 1) + (o2 & 1)) + 3 * (((w >> 1) & 1) + ((o2 >> 1) & 1)) +
+                    9 * (((w >> 2) & 1) + ((o2 >> 2) & 1));
+      touch |= (coarse >> d) & 1u;
+    }
+    cnt += touch;
+  }
+  out[c] = (uint8_t)cnt;
 }
 
 // ------------------------------------------------------------------- march --
@@ -773,7 +801,8 @@ hipError_t build_all(const OctreeTensor& t, const void* values, hipStream_t s) {
     if (e <= b) continue;
     const int64_t blocks = (8 * (e - b) + 255) / 256;
     hipLaunchKernelGGL((corner_kernel<Acc>), dim3((unsigned)blocks), dim3(256), 0, s, T,
-                       (const Acc*)t.centre, (Acc*)t.corners, l, b, e);
+                       (const Acc*)t.centre, (const uint8_t*)t.coarse_corners, (Acc*)t.corners,
+                       l, b, e);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -781,6 +810,19 @@ hipError_t build_all(const OctreeTensor& t, const void* values, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t OctreeTensor::count_coarse_corners(hipStream_t s) {
+  Tree T{child_oct_dev, reinterpret_cast<const int4*>(oct_info), n, (int64_t)n * n * n};
+  for (int l = 1; l <= max_level; ++l) {
+    const int64_t b = level_begin[l], e = level_begin[l + 1];
+    if (e <= b) continue;
+    hipLaunchKernelGGL(coarse_corner_kernel, dim3((unsigned)((e - b + 255) / 256)), dim3(256), 0,
+                       s, T, coarse_corners, l, b, e);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
 
 hipError_t OctreeTensor::build(const void* values, int dtype, hipStream_t s) {
   if (precision == RR_PREC_FP32_KAHAN)

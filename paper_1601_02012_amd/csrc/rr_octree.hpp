@@ -21,11 +21,13 @@ struct OctreeTensor {
   int32_t* oct_info = nullptr;              // per oct: level coords of child 0 (x,y,z), level
   void* centre = nullptr;                   // per cell: 6 components (precision-typed)
   void* corners = nullptr;                  // per cell: 8 x 6 components
+  uint8_t* coarse_corners = nullptr;        // per leaf of level >= 1: corners touching a coarser leaf
   int32_t corner_record_bytes = 0;
   int64_t level_begin[kMaxLevel + 2] = {0};  // first cell index of each level (levels contiguous)
 
   static OctreeTensor* create(const rr_field_desc* f, int precision, rr_status* st,
                               std::string* msg);
+  hipError_t count_coarse_corners(hipStream_t s);   // once, at creation (tree only)
   hipError_t build(const void* values, int dtype, hipStream_t s);
   hipError_t march(const TraceArgs& a, int persistent, int grid_waves, hipStream_t s);
   ~OctreeTensor();

@@ -179,6 +179,18 @@ OctreeTensor* OctreeTensor::create(const rr_field_desc* f, int precision, rr_sta
   e = hipMalloc(&p, rs * 48 * (size_t)n_cells);
   if (e != hipSuccess) goto oom;
   t->corners = p;
+  e = hipMalloc(&p, (size_t)n_cells);
+  if (e != hipSuccess) goto oom;
+  t->coarse_corners = (uint8_t*)p;
+  // the counts depend on the tree only: computed once here, on the null
+  // stream, and waited for (later builds may run on any stream)
+  e = t->count_coarse_corners(nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    *st = RR_ERR_HIP;
+    *msg = std::string("octree corner counts: ") + hipGetErrorString(e);
+    return nullptr;
+  }
   *st = RR_OK;
   return t.release();
 oom:
@@ -191,6 +203,7 @@ OctreeTensor::~OctreeTensor() {
   if (oct_info) (void)hipFree(oct_info);
   if (centre) (void)hipFree(centre);
   if (corners) (void)hipFree(corners);
+  if (coarse_corners) (void)hipFree(coarse_corners);
 }
 
 }  // namespace rr
