@@ -640,6 +640,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     // (the loads are dropped), a coarser one or an edge crossing reloads all
     const int l_in = l;
     const bool single = (int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1;
+    bool inner[3] = {false, false, false};   // a crossed plane inside the new (coarser) leaf
     int kc = T.child[nc];
     bool kept = false;
     if constexpr (kMode != kOctNgp) {
@@ -683,9 +684,17 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         kc = T.child[nc];
       }
       if (lev < l_in) {
-        // coarser neighbour
+        // coarser neighbour.  Across an edge or a vertex, a crossed plane of
+        // level l_in need not be a plane of level lev: along an axis on which
+        // the ray stays within the refined cell's range it runs through the
+        // coarser leaf's interior (there its entry coordinate is not 0)
+        const int mask = (1 << (l_in - lev)) - 1;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) m[k] >>= (l_in - lev);
+        for (int k = 0; k < 3; ++k) {
+          const int plane = r[k] > 0.0 ? m[k] + 1 : m[k];   // the crossed plane, if stepped
+          inner[k] = stepped[k] && (plane & mask) != 0;
+          m[k] >>= (l_in - lev);
+        }
         l = lev;
       }
       if constexpr (kMode != kOctNgp) load_leaf<R, Off>(cv, nc, flip, P, q);
@@ -699,11 +708,14 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         if (stepped[k])
           te[k] = tplane((double)(r[k] > 0.0 ? m[k] : m[k] + 1) * hl, a.o[k], r[k]);
     }
-    // the entry point: on the crossed faces exactly 0, elsewhere the exit
-    // coordinate of the last leaf (same level) or recomputed at the new level
+    // the entry point: on the crossed faces of the new leaf exactly 0,
+    // elsewhere the exit coordinate of the last leaf (same level) or
+    // recomputed at the new level
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      fA[k] = stepped[k] ? (R)0 : (l != l_in ? (R)1 - absd[k] * (R)(chiA - te[k]) : fB[k]);
+      fA[k] = stepped[k] && !inner[k]
+                  ? (R)0
+                  : (l != l_in ? (R)1 - absd[k] * (R)(chiA - te[k]) : fB[k]);
     cell = nc;
   }
   if (!(sum == sum) || sum - sum != (R)0) st = RR_RAY_NONFINITE;

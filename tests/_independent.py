@@ -35,6 +35,32 @@ def crossings(o, d, lo, hi):
     return np.unique(ts)[::-1]
 
 
+def cell_of_piece(o, d, b, a):
+    """Lattice cell holding the piece chi in [b, a] (b < a): per axis the
+    cell whose two planes' parameters t = (m - o) * (1/n) bracket the piece,
+    found from floor of the midpoint and corrected by those parameters (a
+    piece narrower than the rounding of the position stays on its side of a
+    plane).  An axis the ray does not move along keeps floor(o)."""
+    mid = 0.5 * (a + b)
+    m = np.floor(np.asarray(o) + mid * np.asarray(d)).astype(np.int64)
+    for ax in range(3):
+        if d[ax] == 0.0:
+            m[ax] = int(np.floor(o[ax]))
+            continue
+        r = 1.0 / d[ax]
+        for _ in range(4):
+            t0 = (float(m[ax]) - o[ax]) * r
+            t1 = (float(m[ax] + 1) - o[ax]) * r
+            lo_t, hi_t = min(t0, t1), max(t0, t1)
+            if b < lo_t:      # the piece lies at smaller parameters
+                m[ax] += -1 if d[ax] > 0 else 1
+            elif a > hi_t:    # ... at larger parameters
+                m[ax] += 1 if d[ax] > 0 else -1
+            else:
+                break
+    return m
+
+
 def brute_trace(n, tv, o, d, chis, hi, lo, log=False):
     """kappa (and optionally the (cell, chi_a, chi_b) list) of one ray."""
     tv = np.asarray(tv).reshape(n, n, n, 6)
@@ -44,7 +70,7 @@ def brute_trace(n, tv, o, d, chis, hi, lo, log=False):
     segs = []
     for a_, b_ in zip(pts[:-1], pts[1:]):
         mid = 0.5 * (a_ + b_)
-        m = np.floor(np.asarray(o) + mid * np.asarray(d)).astype(np.int64)
+        m = cell_of_piece(o, d, b_, a_)
         half = 0.5 * (a_ - b_)
         chi = mid + half * GL5_X
         p = np.asarray(o)[None, :] + chi[:, None] * np.asarray(d)[None, :]

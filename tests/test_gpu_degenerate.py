@@ -1,0 +1,93 @@
+"""GPU parity on the degenerate cases of the crossing rule (Sec. III E):
+rays along a lattice axis or in a lattice plane (a direction component of
+exactly zero), rays through lattice edges and vertices (two or three planes
+at one parameter), observers on lattice planes and vertices, windows ending
+within rounding of a plane, and windows starting exactly on a plane; on a
+uniform periodic grid (FP64 and FP32-Kahan) and through a refined octree.
+
+Bars as everywhere: crossing hashes and counts bit-exact, FP64 kappa to 1e-11
+of the map's scale, FP32-Kahan within max(1e-5 |kappa|, 1e-7) (potentials at
+cosmological Phi/c^2 amplitudes)."""
+import numpy as np
+import pytest
+
+from paper_1601_02012_amd import inputs as I
+from tests._cases import gpu_bundle, gpu_grid, hashes_u64, kappa_tolerance_ok
+from tests.test_oracle_degenerate import DEGENERATE_DIRS, OBSERVERS, degenerate_case
+
+pytestmark = pytest.mark.gpu
+
+WINDOWS = [(29.0, 0.7), (17.0, 3.0)]
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1601_02012_amd import api as A
+    return A
+
+
+def _check(out, ref, prec):
+    assert np.all(out.status.cpu().numpy() == 0)
+    assert np.array_equal(out.count.cpu().numpy(), ref.ncross)
+    assert np.array_equal(hashes_u64(out.hash), ref.hash)
+    k = out.kappa.double().cpu().numpy()
+    if prec == "fp64":
+        np.testing.assert_allclose(k, ref.kappa, rtol=0, atol=1e-11 * np.abs(ref.kappa).max())
+    else:
+        ok, worst = kappa_tolerance_ok(k, ref.kappa)
+        assert ok, worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_degenerate_rays_uniform(api, oracle, prec):
+    n, phi = degenerate_case()
+    phi = 1e-5 * phi
+    if prec == "fp32":
+        phi = phi.astype(np.float32)
+    tv = oracle.vertex_tensor(phi.astype(np.float64))
+    t = api.TidalTensor(gpu_grid(api, phi, float(n)), prec).build()
+    plan = api.Plan()
+    nd = len(DEGENERATE_DIRS)
+    for obs in OBSERVERS:
+        for hi, lo in WINDOWS:
+            gb = gpu_bundle(api, DEGENERATE_DIRS, nd, 1, 40.0, hi, lo)
+            out = api.trace(plan, t, [gb], obs, debug=True, max_crossings=100000)
+            ref = oracle.trace_uniform(n, float(n), obs, DEGENERATE_DIRS, 40.0, hi, lo, tv=tv)
+            _check(out, ref, prec)
+    # windows that start exactly on a plane, one ray per bundle
+    o = np.array([2.3, 4.1, 1.7])
+    for d in DEGENERATE_DIRS[[0, 4, 5, 7, 10]]:
+        a = int(np.argmax(np.abs(d)))
+        plane = np.floor(o[a] + 20.0 * d[a])
+        hi = float((plane - o[a]) * (1.0 / d[a]))
+        gb = gpu_bundle(api, d[None, :], 1, 1, 40.0, hi, 0.5)
+        out = api.trace(plan, t, [gb], tuple(o), debug=True, max_crossings=100000)
+        ref = oracle.trace_uniform(n, float(n), o, d[None, :], 40.0, hi, 0.5, tv=tv)
+        _check(out, ref, prec)
+    plan.close()
+    t.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_degenerate_rays_octree(api, oracle, prec):
+    from tests.test_gpu_octree import _gpu_octree_grid, _otree, _smooth_phi
+    rng = np.random.default_rng(41)
+    tr = I.random_octree(8, 2, 0.3, rng, region=(1.0, 7.0))
+    box = 8.0
+    phi = _smooth_phi(tr, box, rng)
+    dt = np.float64 if prec == "fp64" else np.float32
+    t = api.TidalTensor(_gpu_octree_grid(api, tr, phi, box, dt), prec).build()
+    ot = _otree(oracle, tr)
+    tc = oracle.centre_tensor_octree(ot, phi.astype(dt).astype(np.float64))
+    plan = api.Plan()
+    nd = len(DEGENERATE_DIRS)
+    for obs in OBSERVERS:
+        for hi, lo in WINDOWS:
+            gb = gpu_bundle(api, DEGENERATE_DIRS, nd, 1, 40.0, hi, lo)
+            out = api.trace(plan, t, [gb], obs, debug=True, max_crossings=100000)
+            ref = oracle.trace_octree(ot, box, obs, DEGENERATE_DIRS, 40.0, hi, lo, tc=tc)
+            _check(out, ref, prec)
+    plan.close()
+    t.close()
