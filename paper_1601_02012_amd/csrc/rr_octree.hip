@@ -710,12 +710,23 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     }
     // the entry point: on the crossed faces of the new leaf exactly 0,
     // elsewhere the exit coordinate of the last leaf (same level) or
-    // recomputed at the new level
+    // recomputed at the new level, and exactly 0 again where that point lies
+    // on the new leaf's entry face (a ray running in a plane of the finer
+    // level), as a pass resuming there sets it
+    const double hl_new = ldexp(1.0, -l);
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      fA[k] = stepped[k] && !inner[k]
-                  ? (R)0
-                  : (l != l_in ? (R)1 - absd[k] * (R)(chiA - te[k]) : fB[k]);
+    for (int k = 0; k < 3; ++k) {
+      if (stepped[k] && !inner[k]) {
+        fA[k] = (R)0;
+      } else if (l != l_in) {
+        fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
+        if (r[k] != 0.0 &&
+            chiA == tplane((double)(r[k] > 0.0 ? m[k] + 1 : m[k]) * hl_new, a.o[k], r[k]))
+          fA[k] = (R)0;
+      } else {
+        fA[k] = fB[k];
+      }
+    }
     cell = nc;
   }
   if (!(sum == sum) || sum - sum != (R)0) st = RR_RAY_NONFINITE;

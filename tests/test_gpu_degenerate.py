@@ -91,3 +91,31 @@ def test_degenerate_rays_octree(api, oracle, prec):
             _check(out, ref, prec)
     plan.close()
     t.close()
+
+
+def test_degenerate_rays_split_march_bitwise(api):
+    """The same rays through the octree with the march split into passes
+    (every ray stops on a face and resumes there, also after edge and vertex
+    crossings into coarser leaves): bitwise the one-pass result."""
+    import torch
+    from tests.test_gpu_octree import _gpu_octree_grid, _smooth_phi
+    rng = np.random.default_rng(41)
+    tr = I.random_octree(8, 2, 0.3, rng, region=(1.0, 7.0))
+    box = 8.0
+    phi = _smooth_phi(tr, box, rng)
+    nd = len(DEGENERATE_DIRS)
+    for prec, dt in (("fp64", np.float64), ("fp32", np.float32)):
+        t = api.TidalTensor(_gpu_octree_grid(api, tr, phi, box, dt), prec).build()
+        for obs in OBSERVERS:
+            res = []
+            for passes in (1, 5):
+                plan = api.Plan()
+                gb = gpu_bundle(api, DEGENERATE_DIRS, nd, 1, 40.0, 29.0, 0.7)
+                plan.set_shape([gb], persistent=0, block=64, passes=passes)
+                out = api.trace(plan, t, [gb], obs, persistent=-1)
+                torch.cuda.synchronize()
+                res.append((out.kappa.cpu().numpy(), out.status.cpu().numpy()))
+                plan.close()
+            assert np.all(res[0][1] == 0)
+            assert np.array_equal(res[0][0], res[1][0]), (prec, obs)
+        t.close()
