@@ -119,3 +119,54 @@ def test_degenerate_rays_split_march_bitwise(api):
             assert np.all(res[0][1] == 0)
             assert np.array_equal(res[0][0], res[1][0]), (prec, obs)
         t.close()
+
+
+def test_degenerate_rays_many_sources(api, oracle):
+    """The many-source walk (Eqs. Isources, Isources1) on the same rays, on
+    the uniform grid and through the octree, with source distances on lattice
+    planes of the axis-aligned rays and inside cells: cut crossing hashes and
+    counts bit-exact per window, FP64 pieces and moments to 1e-11 of their
+    scale."""
+    from tests.test_gpu_octree import _gpu_octree_grid, _otree, _smooth_phi
+    sources = np.array([29.0, 21.3, 17.0, 9.7, 4.0, 1.5])
+    windows = [(29.0, 12.0), (12.0, 0.7)]
+    nd = len(DEGENERATE_DIRS)
+    n, phiu = degenerate_case()
+    phiu = 1e-5 * phiu
+    rng = np.random.default_rng(41)
+    tr = I.random_octree(8, 2, 0.3, rng, region=(1.0, 7.0))
+    phio = _smooth_phi(tr, 8.0, rng)
+    ot = _otree(oracle, tr)
+    cv = oracle.corner_tensor_octree(ot, oracle.centre_tensor_octree(ot, phio))
+    tv = oracle.vertex_tensor(phiu)
+    cases = [("uniform", api.TidalTensor(gpu_grid(api, phiu, float(n)), "fp64").build()),
+             ("octree", api.TidalTensor(_gpu_octree_grid(api, tr, phio, 8.0, np.float64),
+                                        "fp64").build())]
+    plan = api.Plan()
+    for kind, t in cases:
+        for obs in OBSERVERS:
+            state = None
+            mom = pcs = None
+            for hi, lo in windows:
+                gb = gpu_bundle(api, DEGENERATE_DIRS, nd, 1, sources[0], hi, lo)
+                state = api.trace_sources(plan, t, [gb], obs, sources, state=state, debug=True,
+                                          max_crossings=100000)
+                if kind == "uniform":
+                    r = oracle.trace_uniform_sources(n, float(n), obs, DEGENERATE_DIRS, hi, lo,
+                                                     sources, tv=tv, moments=mom, pieces=pcs)
+                else:
+                    r = oracle.trace_octree_sources(ot, 8.0, obs, DEGENERATE_DIRS, hi, lo,
+                                                    sources, cv=cv, moments=mom, pieces=pcs)
+                mom, pcs = r.moments, r.pieces
+                assert np.all(state.status.cpu().numpy() == 0), (kind, obs)
+                assert np.array_equal(state.count.cpu().numpy(), r.ncross), (kind, obs)
+                assert np.array_equal(hashes_u64(state.hash), r.hash), (kind, obs)
+            got_p = state.pieces.cpu().numpy()
+            got_m = state.moments.cpu().numpy()
+            for c in range(2):
+                np.testing.assert_allclose(got_p[..., c], pcs[..., c], rtol=0,
+                                           atol=1e-11 * np.abs(pcs[..., c]).max())
+                np.testing.assert_allclose(got_m[:, c], mom[:, c], rtol=0,
+                                           atol=1e-11 * np.abs(mom[:, c]).max())
+        t.close()
+    plan.close()
