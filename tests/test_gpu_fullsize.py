@@ -240,3 +240,57 @@ def test_adjoint_full_size_sampled_rays(api, oracle):
     assert lhs == pytest.approx(rhs, rel=1e-4)
     t.close()
     plan.close()
+
+
+def test_lightcone_fp64_tensor_above_4gib(api, oracle, lightcone):
+    """The 512^3 light cone's farthest segment with an FP64 tensor (6.4 GB:
+    the march addresses it with 64-bit offsets): sampled rays bit-exact in
+    their crossings and within 1e-11 of the map's scale against the oracle."""
+    import torch
+    n, box, nray, phi0, segs, chi_s, dirs = lightcone
+    hi, lo, s = segs[0]
+    rng = np.random.default_rng(64)
+    sel = np.sort(rng.choice(nray * nray, size=600, replace=False))
+    sdirs = np.ascontiguousarray(dirs[sel])
+    phi = (torch.as_tensor(phi0, device="cuda") * s).to(torch.float32).contiguous()
+    t = api.TidalTensor(api.Grid(phi, box), "fp64").build()
+    assert n ** 3 * 48 >= 1 << 32
+    plan = api.Plan()
+    out = api.trace(plan, t, [api.RayBundle(torch.as_tensor(sdirs, device="cuda"), len(sel), 1,
+                                            chi_s, hi, lo)], (0.0, 0.0, 0.0), debug=True)
+    tv = oracle.vertex_tensor(phi.double().cpu().numpy())
+    ref = oracle.trace_uniform(n, box, (0.0, 0.0, 0.0), sdirs, chi_s, hi, lo, tv=tv)
+    del tv
+    assert np.all(out.status.cpu().numpy() == 0)
+    assert np.array_equal(out.count.cpu().numpy(), ref.ncross)
+    assert np.array_equal(hashes_u64(out.hash), ref.hash)
+    k = out.kappa.cpu().numpy()
+    np.testing.assert_allclose(k, ref.kappa, rtol=0, atol=1e-11 * np.abs(ref.kappa).max())
+    t.close()
+    plan.close()
+
+
+def test_amr_fp64_corner_blocks_above_4gib(api, oracle, amr):
+    """The AMR tree with FP64 corner blocks (20.6 M cells x 384 B = 7.9 GB,
+    64-bit offsets in the octree march): 200 sampled rays of the 4096^2 map
+    bit-exact in their crossings and within 1e-11 of the map's scale."""
+    import torch
+    case, ot, tc, grid, tens = amr
+    assert case.tree.n_cells * 384 >= 1 << 32
+    t64 = api.TidalTensor(grid, "fp64").build()
+    b = I.config3_rays()
+    rng = np.random.default_rng(65)
+    sel = np.sort(rng.choice(b.nx * b.ny, size=200, replace=False))
+    plan = api.Plan()
+    sb = api.RayBundle(torch.as_tensor(b.dirs[sel]).cuda(), len(sel), 1, b.chi_s, b.chi_hi,
+                       b.chi_lo)
+    out = api.trace(plan, t64, [sb], case.observer, debug=True)
+    ref = oracle.trace_octree(ot, case.box, case.observer, b.dirs[sel], b.chi_s, b.chi_hi,
+                              b.chi_lo, tc=tc)
+    assert np.all(out.status.cpu().numpy() == 0)
+    assert np.array_equal(out.count.cpu().numpy(), ref.ncross)
+    assert np.array_equal(hashes_u64(out.hash), ref.hash)
+    k = out.kappa.cpu().numpy()
+    np.testing.assert_allclose(k, ref.kappa, rtol=0, atol=1e-11 * np.abs(ref.kappa).max())
+    t64.close()
+    plan.close()
