@@ -131,7 +131,11 @@ typedef struct rr_plan_s* rr_plan;
  * corner of cell (i,j,k)).  Octree: the child_oct array is copied to the host
  * once to lay out levels and to check 2:1 balance (RR_ERR_OCTREE otherwise);
  * the tensor keeps the device child_oct pointer, which must stay valid while
- * the tensor is used.  Synchronous; allocates device memory. */
+ * the tensor is used (its structure must not change); for every leaf below
+ * level 0 the number of its corners that touch a leaf one level coarser
+ * (N_fv of Eqs. alphac3d, alphaf3d) is counted once here, on the device.
+ * Synchronous (waits for that count on the null stream); allocates device
+ * memory. */
 rr_status rr_tensor_create(const rr_field_desc* f, rr_precision p, rr_tensor* out);
 rr_status rr_tensor_destroy(rr_tensor t);
 
