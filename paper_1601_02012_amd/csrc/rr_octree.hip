@@ -710,9 +710,11 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     }
     // the entry point: on the crossed faces of the new leaf exactly 0,
     // elsewhere the exit coordinate of the last leaf (same level) or
-    // recomputed at the new level, and exactly 0 again where that point lies
-    // on the new leaf's entry face (a ray running in a plane of the finer
-    // level), as a pass resuming there sets it
+    // recomputed at the new level.  In a finer leaf a point can lie exactly
+    // on its entry face along an axis that was not stepped (a ray running in
+    // a plane of the finer level): 0 there too, as a pass resuming at that
+    // point sets it.  (A coarser leaf's entry face holds no such point: along
+    // an axis it moves on, the ray left its entry plane with the last piece.)
     const double hl_new = ldexp(1.0, -l);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -720,7 +722,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         fA[k] = (R)0;
       } else if (l != l_in) {
         fA[k] = (R)1 - absd[k] * (R)(chiA - te[k]);
-        if (r[k] != 0.0 &&
+        if (l > l_in && r[k] != 0.0 &&
             chiA == tplane((double)(r[k] > 0.0 ? m[k] + 1 : m[k]) * hl_new, a.o[k], r[k]))
           fA[k] = (R)0;
       } else {
