@@ -170,3 +170,41 @@ def test_degenerate_rays_many_sources(api, oracle):
                                            atol=1e-11 * np.abs(mom[:, c]).max())
         t.close()
     plan.close()
+
+
+def test_degenerate_rays_method_a_and_isw(api, oracle):
+    """Method A (with its surface terms at the window ends) and the ISW
+    scalar on the same rays and observers, uniform grid, FP64: hashes and
+    counts bit-exact, integrals to 1e-11 of the map's scale."""
+    import torch
+    n, phi = degenerate_case(seed=23)
+    phi = 1e-5 * phi
+    rng = np.random.default_rng(24)
+    delta = rng.normal(size=(n, n, n))
+    prev = 0.97 * phi
+    box = float(n)
+    cdelta = 3e-5
+    gp = api.Grid(torch.as_tensor(phi).cuda(), box)
+    gd = api.Grid(torch.as_tensor(delta).cuda(), box, field="delta")
+    gprev = api.Grid(torch.as_tensor(prev).cuda(), box)
+    gi = api.Grid(gp.values, box, field="phi_dot")
+    ta = api.TidalTensor(gd, "fp64").build_method_a(gd, gp, cdelta)
+    ti = api.TidalTensor(gi, "fp64").build_isw(gp, gprev, 2.0)
+    fv = oracle.method_a_vertex_fields(phi, delta)
+    qv = oracle.isw_vertex_field(phi, prev, 2.0)
+    plan = api.Plan()
+    nd = len(DEGENERATE_DIRS)
+    for obs in OBSERVERS:
+        for hi, lo in WINDOWS:
+            gb = gpu_bundle(api, DEGENERATE_DIRS, nd, 1, 40.0, hi, lo)
+            out = api.trace(plan, ta, [gb], obs, debug=True, max_crossings=100000)
+            ref = oracle.trace_uniform_method_a(n, box, obs, DEGENERATE_DIRS, 40.0, hi, lo,
+                                                delta_coeff=cdelta, fv=fv)
+            _check(out, ref, "fp64")
+            out = api.trace(plan, ti, [gb], obs, quantity="scalar", debug=True,
+                            max_crossings=100000)
+            ref = oracle.trace_uniform_isw(n, box, obs, DEGENERATE_DIRS, hi, lo, qv=qv)
+            _check(out, ref, "fp64")
+    plan.close()
+    ta.close()
+    ti.close()
