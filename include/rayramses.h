@@ -220,7 +220,9 @@ typedef struct {
 } rr_bundle;
 
 typedef struct {
-  double observer[3];        /* observer position in the periodic box */
+  double observer[3];        /* observer position in the periodic box; it and every
+                              window's chi_hi must lie within 2^29 base cells of the
+                              origin (octrees: 2^25), else RR_ERR_INVALID_ARG */
   double kappa_scale;        /* multiplies every per-cell integral */
   int32_t precision;         /* rr_precision, must equal the tensor's */
   int32_t quantity;          /* rr_quantity */

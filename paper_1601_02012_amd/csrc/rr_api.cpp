@@ -399,10 +399,15 @@ rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle
                     : "the trilinear integral reads vertex records (rr_build_tidal_tensor)");
   if (!finite3(tp->observer)) return fail(RR_ERR_NONFINITE, "observer is not finite");
   const double h0 = t->box / (double)t->n;
-  const double cell_cap = (double)(1 << 30);
+  // lattice coordinates are 32-bit on the device, at the finest level of an
+  // octree 2^kMaxLevel times the base-cell ones: keeping the observer and the
+  // far end of every window within 2^(29 - L) base cells of the origin keeps
+  // every coordinate below 2^30
+  const int L = t->kind == RR_GRID_OCTREE ? rr::kMaxLevel : 0;
+  const double cell_cap = (double)(1 << (29 - L));
   for (int k = 0; k < 3; ++k)
     if (std::fabs(tp->observer[k] / h0) > cell_cap)
-      return fail(RR_ERR_INVALID_ARG, "observer is more than 2^30 cells from the origin");
+      return fail(RR_ERR_INVALID_ARG, "observer is more than 2^%d cells from the origin", 29 - L);
   if (!std::isfinite(tp->kappa_scale)) return fail(RR_ERR_NONFINITE, "kappa_scale not finite");
   if (tp->log_stride < 0 || (tp->crossing_log && tp->log_stride == 0))
     return fail(RR_ERR_INVALID_ARG, "crossing_log needs log_stride > 0");
@@ -423,10 +428,10 @@ rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle
                   "bundle %d: need 0 <= chi_lo < chi_hi <= chi_s (got %g, %g, %g)", i, x.chi_lo,
                   x.chi_hi, x.chi_s);
     // a unit ray crosses at most sqrt(3) * window * 2^level planes (+3 at the ends)
-    const double span = (x.chi_hi - x.chi_lo) / h0 * std::sqrt(3.0) *
-                        (double)(1 << (t->kind == RR_GRID_OCTREE ? rr::kMaxLevel : 0));
-    if (x.chi_hi / h0 > cell_cap || span > cell_cap)
-      return fail(RR_ERR_INVALID_ARG, "bundle %d: chi window spans more than 2^30 cells", i);
+    const double span = (x.chi_hi - x.chi_lo) / h0 * std::sqrt(3.0) * (double)(1 << L);
+    if (x.chi_hi / h0 > cell_cap || span > (double)(1 << 30))
+      return fail(RR_ERR_INVALID_ARG, "bundle %d: chi window reaches more than 2^%d cells", i,
+                  29 - L);
   }
   return RR_OK;
 }

@@ -103,3 +103,23 @@ def test_nonfinite_integral(api, prec):
     t_clean.close()
     t_dirty.close()
     plan.close()
+
+
+def test_coordinate_range_rejected(api):
+    """Lattice coordinates are 32-bit on the device: an observer or a window
+    end beyond 2^29 base cells (2^25 for an octree, whose finest level is 16
+    times finer) is rejected on the host before any launch."""
+    plan = api.Plan()
+    for kind, t, _, n in _tensors(api, "fp64"):
+        lim = 2.0 ** (25 if kind == "octree" else 29)
+        h0 = 1.0                                  # both test grids have box = n
+        d = _dirs(2)
+        ok = gpu_bundle(api, d, 2, 1, 30.0, 25.0, 1.0)
+        api.trace(plan, t, [ok], (lim * 0.5 * h0, 0.5, 0.5))
+        with pytest.raises(api.RRError):
+            api.trace(plan, t, [ok], (lim * 2.0 * h0, 0.5, 0.5))
+        far = gpu_bundle(api, d, 2, 1, 4.0 * lim, 3.0 * lim, 1.0)
+        with pytest.raises(api.RRError):
+            api.trace(plan, t, [far], (0.5, 0.5, 0.5))
+        t.close()
+    plan.close()
