@@ -202,3 +202,46 @@ def test_debug_outputs_keep_one_pass(api):
     p1.close()
     p2.close()
     t.close()
+
+
+def test_octree_split_march_in_a_graph_replays(api):
+    """The octree march, persistent and split into passes (the batched
+    configuration's shape), captured in a HIP graph: every replay equals the
+    eager result bit for bit, with the program's own work between replays."""
+    import torch
+    from tests.test_gpu_octree import _gpu_octree_grid, _smooth_phi
+    rng = np.random.default_rng(78)
+    tr = I.random_octree(12, 3, 0.2, rng, region=(2.0, 10.0))
+    box = 24.0
+    phi = _smooth_phi(tr, box, rng)
+    t = api.TidalTensor(_gpu_octree_grid(api, tr, phi, box, np.float32), "fp32").build()
+    d1, d2 = _dirs()
+    b = _bundles(api, d1, d2, 90.0, 90.0, 0.3)
+    obs = (11.7, 12.2, 3.1)
+    ref = _run(api, t, b, obs, None)
+    plan = api.Plan()
+    plan.set_shape(b, persistent=1, waves_per_cu=16, passes=5)
+    nr = 37 * 13 + 9 * 21
+    kap = torch.zeros(nr, dtype=torch.float32, device="cuda")
+    comp = torch.zeros(nr, dtype=torch.float32, device="cuda")
+    st = torch.zeros(nr, dtype=torch.int32, device="cuda")
+    gs = torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        api.trace(plan, t, b, obs, kappa=kap, kappa_comp=comp, status=st, persistent=-1)
+        gs.synchronize()
+        plan.graph_begin()
+        api.trace(plan, t, b, obs, kappa=kap, kappa_comp=comp, status=st, persistent=-1)
+        plan.graph_end()
+    gs.synchronize()
+    for _ in range(3):
+        kap.zero_()
+        comp.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(gs):
+            plan.graph_launch()
+        gs.synchronize()
+        assert np.array_equal(kap.cpu().numpy(), ref[0])
+        assert np.array_equal(comp.cpu().numpy(), ref[1])
+        assert np.array_equal(st.cpu().numpy(), ref[2])
+    plan.close()
+    t.close()
