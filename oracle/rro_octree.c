@@ -2,7 +2,7 @@
  * rro_octree.c -- FP64 oracle for 2:1-balanced AMR octrees.
  * TEST INFRASTRUCTURE ONLY (see rro.h).
  *
- * Readings of the paper taken here (each is listed in the design doc):
+ * Readings of the paper taken here:
  *  - tidal tensor at a level-l cell: Eq. (tidalexample) with the level's cell
  *    size when every stencil cell exists at level l; otherwise that component
  *    is interpolated trilinearly from the eight level-(l-1) centres around the
