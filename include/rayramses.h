@@ -54,7 +54,7 @@ typedef struct ihipStream_t* rr_stream;
 typedef enum {
   RR_OK = 0,
   RR_ERR_INVALID_ARG = -1,   /* null pointer, bad size, chi window not 0 <= lo < hi <= chi_s, ... */
-  RR_ERR_UNSUPPORTED = -2,   /* valid request this build does not implement */
+  RR_ERR_UNSUPPORTED = -2,   /* valid request the library does not implement */
   RR_ERR_OOM = -3,           /* device allocation failed (only in create / first-use calls) */
   RR_ERR_HIP = -4,           /* a HIP runtime call failed; message holds hipGetErrorString */
   RR_ERR_OCTREE = -5,        /* octree malformed or not 2:1 balanced over faces, edges, corners */
