@@ -34,6 +34,16 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_CROSSING = {"fp32": 96, "fp64": 192}     # 4 new corners x 6 components
+# MI355X vector peak: 256 CUs x 4 SIMDs x 32 FP32 lanes x 2 (FMA) x 2.4 GHz;
+# FP64 runs at half that rate
+PEAK_FP32_TFLOPS = 157.3
+# arithmetic of one single-face crossing of the FP32-Kahan march, counted from
+# the method (an FMA counts two): the three-point Gauss integral of the cell
+# (102, scale included), four corner projections P:T (4 x 11), the Kahan
+# update (4) and the local exit coordinates (6) in FP32; the exit selection
+# and tie tests (6 comparisons), exit coordinates (3), the piece length and
+# chi_s - chi_B (2) and the next plane's parameter (2) in FP64
+FLOPS_PER_CROSSING = {"fp32": 156, "fp64": 13}
 BYTES_PER_VERTEX = {"fp32": 4 + 24, "fp64": 4 + 48}  # potential in, 6 components out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_traffic.md")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_counters.md")
@@ -648,7 +658,9 @@ def main():
     value = r32["cross"] / (r32["step_ms"] * 1e-3)
     march_launch_ms = r32["march_ms"] / nseg
     cross_per_launch = r32["cross"] / nseg
-    achieved = BYTES_PER_CROSSING["fp32"] * cross_per_launch / (march_launch_ms * 1e-3) / 1e9
+    bytes_gbs = BYTES_PER_CROSSING["fp32"] * cross_per_launch / (march_launch_ms * 1e-3) / 1e9
+    flops_eq = FLOPS_PER_CROSSING["fp32"] + 2 * FLOPS_PER_CROSSING["fp64"]
+    achieved = flops_eq * cross_per_launch / (march_launch_ms * 1e-3) / 1e12
     prof = profile_figures()
     traffic = prof.get("hbm_bytes_per_launch")
     out = {
@@ -670,8 +682,11 @@ def main():
                                "grid every segment, FP32-Kahan march",
                    "grid": ctx["n"], "rays": args.rays ** 2, "segments": nseg,
                    "chi_s": ctx["chi_s"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "flops_per_crossing": {**FLOPS_PER_CROSSING, "fp32_equivalent": flops_eq},
+                     "bytes_model": {"achieved": bytes_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                     "frac": bytes_gbs / PEAK_HBM_GBS},
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
                                      "copy-calibrated)",
