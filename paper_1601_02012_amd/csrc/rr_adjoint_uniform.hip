@@ -66,30 +66,28 @@ __device__ __forceinline__ float dpp_lane(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xf, 0xf, false));
 }
 
-// Sum over the 64 lanes (every lane active), returned as a wavefront-uniform
-// value.  Within each row of 16 lanes: add lane i ^ 1, lane i ^ 2 (quad
-// permutes), then the mirrored lane of the half row (the other quad of eight)
-// and of the row (the other eight); the four row sums are then read out of
-// lanes 0, 16, 32 and 48.  Lane moves, no LDS traffic.
-__device__ __forceinline__ float wave_sum(float x) {
-  x += dpp_lane<0xb1>(x);    // quad_perm [1,0,3,2]
-  x += dpp_lane<0x4e>(x);    // quad_perm [2,3,0,1]
-  x += dpp_lane<0x141>(x);   // row_half_mirror
-  x += dpp_lane<0x140>(x);   // row_mirror
-  const int b = __float_as_int(x);
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(b, 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(b, 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(b, 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(b, 48));
-  return (r0 + r1) + (r2 + r3);
+// One step of a wavefront reduce-scatter over 2 kHalf values per lane: the
+// lane sends the half of its values it does not keep to the lane that the DPP
+// pattern kCtrl reads it from, and adds the same half of its own source's
+// values to the half it keeps (the high half if `hi`).  Source and receiver
+// differ in exactly the bit that picks the half.
+template <int kCtrl, int kHalf>
+__device__ __forceinline__ void fold(float* x, bool hi) {
+#pragma unroll
+  for (int i = 0; i < kHalf; ++i) {
+    const float keep = hi ? x[i + kHalf] : x[i];
+    const float send = hi ? x[i] : x[i + kHalf];
+    x[i] = keep + dpp_lane<kCtrl>(send);
+  }
 }
 
 // A wavefront's cache of retired vertex sums in LDS, direct-mapped on the low
-// bits of the vertex coordinates: the lanes of a tile drift apart by a step
-// or two, so a vertex is often retired by several groups of lanes a few steps
-// apart; their sums meet in the cache, and a vertex goes to global memory
-// (six FP32 atomics) when its slot is taken by another vertex or the tile
-// ends.  Only group leaders touch it, one at a time.
+// bits of the vertex coordinates (taken before the periodic wrap, so the
+// corners of one cell always fall in distinct slots): the lanes of a tile
+// drift apart by a step or two, so a vertex is often retired by several
+// groups of lanes a few steps apart; their sums meet in the cache, and a
+// vertex goes to global memory (six FP32 atomics) when its slot is taken by
+// another vertex or the tile ends.
 struct CacheSlot {
   uint64_t tag;   // vertex id, or kEmpty
   float v[6];
@@ -105,43 +103,73 @@ __device__ __forceinline__ void flush_slot(float* __restrict__ lam, const CacheS
   }
 }
 
-// Retire one corner of every lane that has weight on it (acc != 0): its six
-// tensor components get acc * P_ab.  The rays of a tile run side by side and
-// every cell is crossed by many rays, so per-lane atomics on one address
-// would serialise: the retiring lanes are grouped by vertex (one group per
-// distinct vertex, usually one or two per wavefront), each group's six sums
-// are reduced across the wavefront and its first lane adds them to the
-// wavefront's cache.  Called with all 64 lanes active (acc = 0 for lanes
-// that retire nothing, including lanes whose ray has ended).
-__device__ __forceinline__ void flush_corner(float* __restrict__ lam, CacheSlot* cache,
-                                             uint64_t vid, int slot, float acc, const float* P,
-                                             int lane) {
-  bool want = acc != 0.0f;
-  unsigned long long m = __ballot(want);
-  while (m != 0ull) {
-    const int leader = __builtin_ctzll(m);
-    const uint64_t lv =
-        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(vid >> 32), leader) << 32) |
-        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)vid, leader);
-    const int ls = __builtin_amdgcn_readlane(slot, leader);
-    const bool mine = want && vid == lv;
-    float sums[6];
+// Corner v = ix + 2 iy + 4 iz of a cell that is the j-th corner (j = 0..3,
+// ordered by the two coordinates along the face) of face F = 2 axis + side.
+__device__ __forceinline__ int face_corner(int F, int j) {
+  const int k = F >> 1, s = F & 1;
+  return k == 0 ? (s | (j << 1)) : (k == 1 ? ((j & 1) | (s << 1) | ((j >> 1) << 2)) : (j | (s << 2)));
+}
+
+// Retire face F of cell (W0, W1, W2) for the lanes with `mine` set: corner j
+// of the face gets sum over those lanes of acc_v * P_ab.  The 4 x 6 sums are
+// reduced jointly over the wavefront: three halving steps (lane bits 0, 1
+// and 2, lane moves within quads and rows) leave every lane with 3 of the 24
+// values summed over 8 lanes, which the row (bit 3) and the two other
+// 16-lane groups then complete; lanes 0..7 hold all 24 sums, corner
+// 2 b0 + b1 and components 3 b2 .. 3 b2 + 2, and update the cache side by
+// side.  Called with all 64 lanes active; F and W are wavefront-uniform.
+__device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* cache,
+                                            const float* acc, const float* P, bool mine, int F,
+                                            int W0, int W1, int W2, int n, int lane) {
+  float a[4];
+  switch (F) {
+    case 0: a[0] = acc[0]; a[1] = acc[2]; a[2] = acc[4]; a[3] = acc[6]; break;
+    case 1: a[0] = acc[1]; a[1] = acc[3]; a[2] = acc[5]; a[3] = acc[7]; break;
+    case 2: a[0] = acc[0]; a[1] = acc[1]; a[2] = acc[4]; a[3] = acc[5]; break;
+    case 3: a[0] = acc[2]; a[1] = acc[3]; a[2] = acc[6]; a[3] = acc[7]; break;
+    case 4: a[0] = acc[0]; a[1] = acc[1]; a[2] = acc[2]; a[3] = acc[3]; break;
+    default: a[0] = acc[4]; a[1] = acc[5]; a[2] = acc[6]; a[3] = acc[7]; break;
+  }
+  float x[24];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sums[c] = wave_sum(mine ? acc * P[c] : 0.0f);
-    if (lane == leader) {
-      CacheSlot& e = cache[ls];
-      if (e.tag == lv) {
+  for (int j = 0; j < 4; ++j) {
+    const float aj = mine ? a[j] : 0.0f;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) e.v[c] += sums[c];
-      } else {
-        flush_slot(lam, e);
-        e.tag = lv;
+    for (int c = 0; c < 6; ++c) x[6 * j + c] = aj * P[c];
+  }
+  fold<0xb1, 12>(x, (lane & 1) != 0);    // quad_perm [1,0,3,2]: lane ^ 1
+  fold<0x4e, 6>(x, (lane & 2) != 0);     // quad_perm [2,3,0,1]: lane ^ 2
+  fold<0x124, 3>(x, (lane & 4) != 0);    // row_ror:4: lane - 4 within the row
 #pragma unroll
-        for (int c = 0; c < 6; ++c) e.v[c] = sums[c];
+  for (int i = 0; i < 3; ++i) {
+    x[i] += dpp_lane<0x128>(x[i]);       // row_ror:8: lane ^ 8
+    x[i] += __shfl_xor(x[i], 16);
+    x[i] += __shfl_xor(x[i], 32);
+  }
+  if (lane < 8) {
+    const int j = 2 * (lane & 1) + ((lane >> 1) & 1);
+    const int cb = (lane & 4) ? 3 : 0;
+    const int v = face_corner(F, j);
+    int cx = W0 + (v & 1), cy = W1 + ((v >> 1) & 1), cz = W2 + (v >> 2);
+    const int slot = (cx & 7) | ((cy & 7) << 3) | ((cz & 3) << 6);
+    cx = cx == n ? 0 : cx;
+    cy = cy == n ? 0 : cy;
+    cz = cz == n ? 0 : cz;
+    const uint64_t vid = ((uint64_t)cz * (uint64_t)n + (uint64_t)cy) * (uint64_t)n + (uint64_t)cx;
+    CacheSlot& e = cache[slot];
+    const uint64_t tag = e.tag;
+    if (tag == vid) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) e.v[cb + i] += x[i];
+    } else {
+      if (tag != kEmpty) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) atomicAdd(lam + tag * 6 + cb + i, e.v[cb + i]);
       }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) e.v[cb + i] = x[i];
+      if (cb == 0) e.tag = vid;
     }
-    want = want && !mine;
-    m = __ballot(want);
   }
 }
 
@@ -175,13 +203,10 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
   for (int c = 0; c < 6; ++c) P[c] = (float)Pd[c] * wr;
 
   const int n = a.n;
-  const uint64_t nI = (uint64_t)n, nnI = nI * nI;
-  const uint64_t stride[3] = {1, nI, nnI};
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
   double r[3], pe[3], te[3], cpos[3], sgn[3];
   int w[3];
-  uint64_t off0[3], off1[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     r[k] = (d[k] != 0.0) ? 1.0 / d[k] : 0.0;
@@ -192,14 +217,13 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
     cpos[k] = a.o[k] - (double)m;
     const int ww = m % n;
     w[k] = ww < 0 ? ww + n : ww;
-    off0[k] = (uint64_t)w[k] * stride[k];
-    off1[k] = (uint64_t)(w[k] + 1 == n ? 0 : w[k] + 1) * stride[k];
   }
   float uA[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) uA[k] = (float)fma(chiA, d[k], cpos[k]);
   const float inv_chis = (float)(1.0 / B.chi_s);
   const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
+  const int dpos = (d[0] > 0.0 ? 1 : 0) | (d[1] > 0.0 ? 2 : 0) | (d[2] > 0.0 ? 4 : 0);
   float acc[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) acc[v] = 0.0f;
@@ -210,7 +234,9 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
     bool stepped[3] = {false, false, false};
     float uB[3] = {0.0f, 0.0f, 0.0f};
     double chiB = lo;
-    int retire = 0;
+    // the corners that retire are one face of the cell, F = 2 axis + side,
+    // or all eight (both z faces, f0 = 4 and f1 = 5)
+    int f0 = -1, f1 = -1;
     int kk = -1;
     bool last = false;
     if (alive) {
@@ -238,42 +264,37 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
         const int nstep = (int)stepped[0] + (int)stepped[1] + (int)stepped[2];
         // corners that retire: all eight at the end of the ray or after an
         // edge/vertex crossing; after a single-axis step along k the face the
-        // ray leaves behind (the crossed face is shared with the next cell)
-        retire = 0xff;
+        // ray leaves behind (the crossed face is shared with the next cell;
+        // the ray moves along -d, so it leaves the high face when d_k > 0)
         if (!last && nstep == 1) {
           kk = stepped[0] ? 0 : (stepped[1] ? 1 : 2);
-          const int bit = 1 << kk;
-          const int keep = d[kk] > 0.0 ? 0 : bit;   // corners on the crossed face
-          retire = 0;
-#pragma unroll
-          for (int v = 0; v < 8; ++v)
-            if ((v & bit) != keep) retire |= 1 << v;
+          f0 = 2 * kk + ((dpos >> kk) & 1);
+        } else {
+          f0 = 4;
+          f1 = 5;
         }
       }
     }
-    if (stopped) retire = 0xff;
-    // corner ids of the current cell (v = ix + 2 iy + 4 iz)
-    uint64_t vid[8];
-    int slot[8];
-    {
-      int cx[2], cy[2], cz[2];
-      cx[0] = w[0]; cx[1] = w[0] + 1 == n ? 0 : w[0] + 1;
-      cy[0] = w[1]; cy[1] = w[1] + 1 == n ? 0 : w[1] + 1;
-      cz[0] = w[2]; cz[1] = w[2] + 1 == n ? 0 : w[2] + 1;
-#pragma unroll
-      for (int v = 0; v < 8; ++v)
-        slot[v] = (cx[v & 1] & 7) | ((cy[(v >> 1) & 1] & 7) << 3) | ((cz[v >> 2] & 3) << 6);
+    if (stopped) {
+      f0 = 4;
+      f1 = 5;
     }
-    {
-      const uint64_t zy00 = off0[2] + off0[1], zy01 = off0[2] + off1[1];
-      const uint64_t zy10 = off1[2] + off0[1], zy11 = off1[2] + off1[1];
-      vid[0] = zy00 + off0[0]; vid[1] = zy00 + off1[0]; vid[2] = zy01 + off0[0];
-      vid[3] = zy01 + off1[0]; vid[4] = zy10 + off0[0]; vid[5] = zy10 + off1[0];
-      vid[6] = zy11 + off0[0]; vid[7] = zy11 + off1[0];
+    // one round per distinct (cell, face) among the lanes, usually one
+    for (;;) {
+      const unsigned long long m = __ballot(f0 >= 0);
+      if (m == 0ull) break;
+      const int leader = __builtin_ctzll(m);
+      const int F = __builtin_amdgcn_readlane(f0, leader);
+      const int W0 = __builtin_amdgcn_readlane(w[0], leader);
+      const int W1 = __builtin_amdgcn_readlane(w[1], leader);
+      const int W2 = __builtin_amdgcn_readlane(w[2], leader);
+      const bool mine = f0 == F && w[0] == W0 && w[1] == W1 && w[2] == W2;
+      retire_face(lam, cache, acc, P, mine, F, W0, W1, W2, n, lane);
+      if (mine) {
+        f0 = f1;
+        f1 = -1;
+      }
     }
-#pragma unroll
-    for (int v = 0; v < 8; ++v)
-      flush_corner(lam, cache, vid[v], slot[v], ((retire >> v) & 1) ? acc[v] : 0.0f, P, lane);
     if (stopped) {
 #pragma unroll
       for (int v = 0; v < 8; ++v) acc[v] = 0.0f;
@@ -315,8 +336,6 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
         int ww = w[k] + s;
         ww = ww < 0 ? ww + n : (ww >= n ? ww - n : ww);
         w[k] = ww;
-        off0[k] = (uint64_t)ww * stride[k];
-        off1[k] = (uint64_t)(ww + 1 == n ? 0 : ww + 1) * stride[k];
       }
     }
     chiA = chiB;
