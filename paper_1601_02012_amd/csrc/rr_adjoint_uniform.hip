@@ -130,14 +130,18 @@ __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* 
     case 4: a[0] = acc[0]; a[1] = acc[1]; a[2] = acc[2]; a[3] = acc[3]; break;
     default: a[0] = acc[4]; a[1] = acc[5]; a[2] = acc[6]; a[3] = acc[7]; break;
   }
-  float x[24];
+  // the first halving step is taken on the products as they are formed: a
+  // lane with bit 0 set keeps corners 2 and 3 and sends 0 and 1, a lane
+  // with it clear the reverse
+  const bool h0 = (lane & 1) != 0;
+  float x[12];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float aj = mine ? a[j] : 0.0f;
+  for (int j = 0; j < 2; ++j) {
+    const float al = mine ? a[j] : 0.0f, ah = mine ? a[j + 2] : 0.0f;
+    const float keep = h0 ? ah : al, send = h0 ? al : ah;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) x[6 * j + c] = aj * P[c];
-  }
-  fold<0xb1, 12>(x, (lane & 1) != 0);    // quad_perm [1,0,3,2]: lane ^ 1
+    for (int c = 0; c < 6; ++c) x[6 * j + c] = fmaf(keep, P[c], dpp_lane<0xb1>(send * P[c]));
+  }                                      // quad_perm [1,0,3,2]: lane ^ 1
   fold<0x4e, 6>(x, (lane & 2) != 0);     // quad_perm [2,3,0,1]: lane ^ 2
   fold<0x124, 3>(x, (lane & 4) != 0);    // row_ror:4: lane - 4 within the row
 #pragma unroll
@@ -205,15 +209,17 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
   const int n = a.n;
   const double lo = B.chi_lo;
   double chiA = B.chi_hi;
-  double r[3], pe[3], te[3], cpos[3], sgn[3];
+  // per axis: bit k of dpos set when d_k > 0 (the march runs down the lattice)
+  const int dpos = (d[0] > 0.0 ? 1 : 0) | (d[1] > 0.0 ? 2 : 0) | (d[2] > 0.0 ? 4 : 0);
+  double r[3], te[3], cpos[3];
+  int px[3];   // lattice coordinate of the exit plane
   int w[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     r[k] = (d[k] != 0.0) ? 1.0 / d[k] : 0.0;
     const int m = start_slab(a.o[k], d[k], r[k], chiA, 1.0);
-    sgn[k] = d[k] > 0.0 ? -1.0 : 1.0;
-    pe[k] = (double)(d[k] > 0.0 ? m : m + 1);
-    te[k] = d[k] != 0.0 ? tplane(pe[k], a.o[k], r[k]) : -__builtin_inf();
+    px[k] = d[k] > 0.0 ? m : m + 1;
+    te[k] = d[k] != 0.0 ? tplane((double)px[k], a.o[k], r[k]) : -__builtin_inf();
     cpos[k] = a.o[k] - (double)m;
     const int ww = m % n;
     w[k] = ww < 0 ? ww + n : ww;
@@ -223,7 +229,6 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
   for (int k = 0; k < 3; ++k) uA[k] = (float)fma(chiA, d[k], cpos[k]);
   const float inv_chis = (float)(1.0 / B.chi_s);
   const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
-  const int dpos = (d[0] > 0.0 ? 1 : 0) | (d[1] > 0.0 ? 2 : 0) | (d[2] > 0.0 ? 4 : 0);
   float acc[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) acc[v] = 0.0f;
@@ -251,7 +256,7 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
         for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const float face = d[k] > 0.0 ? 0.0f : 1.0f;
+          const float face = ((dpos >> k) & 1) ? 0.0f : 1.0f;
           uB[k] = stepped[k] ? face : (float)fma(chiB, d[k], cpos[k]);
         }
         float om[8];
@@ -314,7 +319,7 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
       for (int k = 0; k < 3; ++k) {
         if (k != kk) continue;
         const int bit = 1 << k;
-        const int keep = d[k] > 0.0 ? 0 : bit;
+        const int keep = ((dpos >> k) & 1) ? 0 : bit;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
           if ((v & bit) != keep) {
@@ -328,11 +333,12 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
     for (int k = 0; k < 3; ++k) {
       uA[k] = uB[k];
       if (stepped[k]) {
-        pe[k] += sgn[k];
-        te[k] = tplane(pe[k], a.o[k], r[k]);
-        cpos[k] -= sgn[k];
+        const bool down = (dpos >> k) & 1;
+        px[k] += down ? -1 : 1;
+        te[k] = tplane((double)px[k], a.o[k], r[k]);
+        cpos[k] += down ? 1.0 : -1.0;
         uA[k] = 1.0f - uB[k];
-        const int s = d[k] > 0.0 ? -1 : 1;
+        const int s = down ? -1 : 1;
         int ww = w[k] + s;
         ww = ww < 0 ? ww + n : (ww >= n ? ww - n : ww);
         w[k] = ww;
