@@ -114,10 +114,10 @@ __device__ __forceinline__ int face_corner(int F, int j) {
 // of the face gets sum over those lanes of acc_v * P_ab.  The 4 x 6 sums are
 // reduced jointly over the wavefront: three halving steps (lane bits 0, 1
 // and 2, lane moves within quads and rows) leave every lane with 3 of the 24
-// values summed over 8 lanes, which the row (bit 3) and the two other
-// 16-lane groups then complete; lanes 0..7 hold all 24 sums, corner
-// 2 b0 + b1 and components 3 b2 .. 3 b2 + 2, and update the cache side by
-// side.  Called with all 64 lanes active; F and W are wavefront-uniform.
+// values summed over 8 lanes, which the row (bit 3) and the other rows
+// (register swaps of 16- and 32-lane groups) then complete; lanes 0..7 hold
+// all 24 sums, corner 2 b0 + b1 and components 3 b2 .. 3 b2 + 2, and update
+// the cache side by side.  Called with all 64 lanes active; F and W are wavefront-uniform.
 __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* cache,
                                             const float* acc, const float* P, bool mine, int F,
                                             int W0, int W1, int W2, int n, int lane) {
@@ -147,8 +147,14 @@ __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* 
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     x[i] += dpp_lane<0x128>(x[i]);       // row_ror:8: lane ^ 8
-    x[i] += __shfl_xor(x[i], 16);
-    x[i] += __shfl_xor(x[i], 32);
+    // the 16-lane rows and then the 32-lane halves swapped in registers: the
+    // two results hold x of the lane and of lane ^ 16 (^ 32), in either order
+    const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[i]), __float_as_uint(x[i]),
+                                                      false, false);
+    x[i] = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+    const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[i]),
+                                                      false, false);
+    x[i] = __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
   }
   if (lane < 8) {
     const int j = 2 * (lane & 1) + ((lane >> 1) & 1);
