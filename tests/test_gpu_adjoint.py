@@ -40,6 +40,11 @@ def _case(seed, n, box, nray, fov_deg, center=(0.0, 0.0, 1.0)):
 @pytest.mark.parametrize("seed,n,box,nray,fov,obs,chi", [
     (0, 32, 64.0, 24, 6.0, (0.0, 0.0, 0.0), (70.0, 60.0, 0.0)),
     (1, 24, 24.0, 19, 30.0, (3.3, 5.1, 2.2), (30.0, 20.0, 1.5)),
+    # grids where the periodic wrap would put two corners of a cell on the
+    # same low coordinate bits (9 = 1 mod 8 in x and y, 5 = 1 mod 4 in z);
+    # an observer on a vertex; ragged ray tiles
+    (2, 9, 13.5, 13, 30.0, (4.5, 3.0, 1.5), (20.0, 18.0, 2.0)),
+    (3, 5, 5.0, 7, 60.0, (1.3, 2.7, 0.4), (8.0, 7.0, 0.5)),
 ])
 def test_adjoint_matches_oracle_gradient(api, oracle, plan, seed, n, box, nray, fov, obs, chi):
     import torch
