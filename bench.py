@@ -125,10 +125,13 @@ def lightcone_leg(args, api, I, torch, dev):
         st = torch.zeros(nr, dtype=torch.int32, device=dev)
         total_cross = 0
         shapes = []
+        seg_hash = []
         for k in range(len(segs)):
             t.build(grids[k])
             o = api.trace(plan, t, bundles[k], obs, debug=True, persistent=0)
             total_cross += int(o.count.sum().item())
+            if fp32:
+                seg_hash.append((o.hash, o.count))   # kept on the device for the oracle check
             del o
             if args.tune_lightcone:
                 shapes.append(plan.autotune(t, bundles[k], obs))
@@ -163,7 +166,7 @@ def lightcone_leg(args, api, I, torch, dev):
                 cross=total_cross, step_ms=step_ms, build_ms=build_ms, march_ms=march_ms,
                 kappa=kap.double().cpu().numpy(), status_ok=bool((st == 0).all().item()),
                 shapes=[(s["persistent"], s["block"], s["waves_per_cu"]) for s in shapes],
-                box_frac=frac)
+                box_frac=frac, seg_hash=seg_hash)
         t.close()
         del kap, comp, st
         torch.cuda.empty_cache()
@@ -561,22 +564,47 @@ def amr_profile(args, api, I, torch, dev):
     return {"amr_profile": {"passes": args.amr_passes, "ms": ms, "cells": int(tr.n_cells)}}
 
 
+def host_cpu():
+    """Model name, sockets and the cores this process may run on (the oracle's
+    OpenMP threads), from /proc/cpuinfo and the scheduler affinity."""
+    model, sockets = "unknown", set()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name") and model == "unknown":
+                model = line.split(":", 1)[1].strip()
+            elif line.startswith("physical id"):
+                sockets.add(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit():
+        cores = min(cores, int(omp))
+    return model, max(len(sockets), 1), max(int(cores or 1), 1)
+
+
 def cpu_baseline(ctx, results, target_s):
     """FP64 oracle on the host over the whole light cone (every segment with
-    its own vertex tensor) for a deterministic ray sample."""
+    its own vertex tensor) for a deterministic ray sample, on all the cores
+    this process may use, and on one thread for a smaller sample; the GPU's
+    crossing hashes and counts of the sampled rays (from the full-map launch
+    with hashes) are compared with the oracle's in every segment."""
     from oracle import oracle as O
     phis, segs, dirs = ctx["phis"], ctx["segs"], ctx["dirs"]
     n, box, obs, chi_s = ctx["n"], ctx["box"], ctx["obs"], ctx["chi_s"]
-    cores = os.cpu_count() or 1
+    model, sockets, cores = host_cpu()
     r32 = results["fp32"]
     per_ray = r32["cross"] / dirs.shape[0]
     # sample size for about target_s of tracing at ~1e7 crossings/s per core
     want = int(min(dirs.shape[0], max(4096, target_s * 1.0e7 * cores / per_ray)))
     rng = np.random.default_rng(12345)
     sel = np.sort(rng.choice(dirs.shape[0], size=want, replace=False))
+    # one-thread sample: every 64th ray of the sample's first 1/8 (a few seconds)
+    one = sel[: max(64, want // 8)][::64]
     kap = np.zeros(want)
-    t_tensor = t_trace = 0.0
-    cross = 0
+    t_tensor = t_trace = t_one = 0.0
+    cross = cross_one = 0
+    hash_ok = count_ok = True
     for k, (hi, lo, _) in enumerate(segs):
         phi = phis[k].double().cpu().numpy()
         t0 = time.perf_counter()
@@ -585,22 +613,40 @@ def cpu_baseline(ctx, results, target_s):
         t0 = time.perf_counter()
         r = O.trace_uniform(n, box, obs, dirs[sel], chi_s, hi, lo, tv=tv, threads=cores)
         t_trace += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r1 = O.trace_uniform(n, box, obs, dirs[one], chi_s, hi, lo, tv=tv, threads=1)
+        t_one += time.perf_counter() - t0
+        cross_one += int(r1.ncross.sum())
         kap += r.kappa
         cross += int(r.ncross.sum())
+        gh, gc = r32["seg_hash"][k]
+        hash_ok &= bool(np.array_equal(gh.cpu().numpy().view(np.uint64)[sel], r.hash))
+        count_ok &= bool(np.array_equal(gc.cpu().numpy()[sel], r.ncross))
         del tv
-        log(f"oracle segment {k}: {int(r.ncross.sum())} crossings")
+        log(f"oracle segment {k}: {int(r.ncross.sum())} crossings, hashes equal: {hash_ok}")
     log(f"oracle: {want} rays x {len(segs)} segments, {cross} crossings in {t_trace:.1f}s "
-        f"(+{t_tensor:.1f}s tensors)")
+        f"(+{t_tensor:.1f}s tensors); one thread: {cross_one} crossings in {t_one:.1f}s")
     gk = r32["kappa"][sel]
     err = np.abs(gk - kap)
     lim = np.maximum(1e-5 * np.abs(kap), 1e-7)
     cb = {"value": cross / t_trace, "unit": "crossings/s", "cores": cores, "kind": "oracle",
           "sample": f"{want} of {dirs.shape[0]} rays through all {len(segs)} chi segments of "
-                    f"the light cone ({cross} crossings); FP64 C oracle, OpenMP over rays; its "
-                    f"{len(segs)} vertex tensors ({n}^3 each) took {t_tensor:.1f}s, not included",
-          "ns_per_crossing_per_core": t_trace * cores / cross * 1e9}
+                    f"the light cone ({cross} crossings); FP64 C oracle, OpenMP over rays on "
+                    f"{cores} threads; its {len(segs)} vertex tensors ({n}^3 each) took "
+                    f"{t_tensor:.1f}s, not included",
+          "cpu_model": model, "sockets": sockets,
+          "ns_per_crossing_one_thread": t_one / cross_one * 1e9,
+          "one_thread_sample": f"{one.size} rays (every 64th of the sample's first eighth) "
+                               f"through all {len(segs)} segments, {cross_one} crossings, "
+                               "measured on one thread",
+          "ns_per_crossing_per_core_derived": t_trace * cores / cross * 1e9,
+          "ns_per_crossing_per_core_derived_note": "all-thread time x threads / crossings "
+                                                  "(derived, not measured per core)"}
     par = {"rays": int(want), "kappa_max_err_over_tol": float(np.max(err / lim)),
-           "tolerance": "max(1e-5 |kappa|, 1e-7) per ray, FP32-Kahan GPU vs FP64 oracle"}
+           "crossing_hashes_equal": hash_ok, "crossing_counts_equal": count_ok,
+           "segments": len(segs),
+           "tolerance": "max(1e-5 |kappa|, 1e-7) per ray, FP32-Kahan GPU vs FP64 oracle; "
+                        "crossing hashes and counts bit-exact in every segment"}
     return cb, par
 
 

@@ -10,7 +10,7 @@
  * one piece per crossed cell (Eqs. (sumIc), (Ic)); inside a cell the integrand
  * is the trilinear reconstruction from the cell's eight vertex values
  * (Eq. trilinear_int), and the vertex values are interpolated from cell
- * centres (Sec. III F; Eqs. (alphac3d), (alphaf3d) at refinement boundaries).
+ * centres (Sec. III H; Eqs. (alphac3d), (alphaf3d) at refinement boundaries).
  *
  * Conventions shared by every entry point
  *  - Pointers named "device" are HIP device pointers owned by the caller; the
@@ -141,19 +141,19 @@ rr_status rr_tensor_destroy(rr_tensor t);
 
 /* Tidal tensor at cell centres by central finite differences (Eq.
  * tidalexample, cell size of the cell's own level) and its interpolation to
- * cell vertices (Sec. III F).  Octree cells whose stencil is incomplete at
+ * cell vertices (Sec. III H).  Octree cells whose stencil is incomplete at
  * their level take the trilinear interpolation of the coarser level's
  * component (Sec. IV C, second approach).  f must describe the same grid as
  * at rr_tensor_create; values may change between calls (one call per N-body
  * step).  Asynchronous on s; no allocation. */
 rr_status rr_build_tidal_tensor(rr_tensor t, const rr_field_desc* f, rr_stream s);
 
-/* Method A (Sec. IV C, Eq. kappa2): kappa from the density contrast and the
+/* Method A (Sec. IV D, Eq. kappa2): kappa from the density contrast and the
  * potential's gradient instead of the tidal tensor.  The tensor is created
  * from a density descriptor (field RR_FIELD_DELTA, uniform grids only) and
  * holds per vertex (delta_coeff delta, dPhi/dx, dPhi/dy, dPhi/dz): cell
  * values of delta, gradients by central differences, both averaged over the
- * eight incident cells (Sec. III F).  delta_coeff multiplies delta into the
+ * eight incident cells (Sec. III H).  delta_coeff multiplies delta into the
  * Laplacian of phi's units, in 1 / length^2 of the box unit (for phi = Phi/c^2:
  * 3/2 Omega_m (H0/c)^2 / a).  rr_trace_rays then adds, per ray and chi
  * segment, int g delta_coeff delta + int (n . grad phi) dg/dchi (kernel
@@ -169,7 +169,7 @@ rr_status rr_build_method_a_fields(rr_tensor t, const rr_field_desc* delta,
  * potential, by finite differences between N-body steps).  The tensor is
  * created from a descriptor with field RR_FIELD_PHI_DOT (uniform grids) and
  * holds per vertex the mean over its eight cells of
- * (phi_curr - phi_prev) * inv_dt (Sec. III F); open grids leave the vertices
+ * (phi_curr - phi_prev) * inv_dt (Sec. III H); open grids leave the vertices
  * on the lower faces NaN.  rr_trace_rays with quantity RR_Q_SCALAR and the
  * trilinear integral then adds kappa_scale * int Q dchi (chi in the box's
  * length unit) per ray over its window: the paper gives no kernel K for this
@@ -193,7 +193,7 @@ rr_status rr_build_tidal_tensor_centres(rr_tensor t, const rr_field_desc* f, rr_
  * box wraps; 0 <= size[a] <= n).  Vertices outside the box keep the values
  * of earlier builds.  The rays of one N-body step only read the vertices
  * around their chi segment (rr_rays_vertex_box), and the tensor work can be
- * limited to them (Sec. III F: the interpolation is worth doing only where
+ * limited to them (Sec. III H: the interpolation is worth doing only where
  * rays need it).  Uniform grids only (RR_ERR_UNSUPPORTED otherwise); open
  * grids take boxes inside [0, n) (RR_ERR_DOMAIN).  Asynchronous on s; no
  * allocation. */
@@ -208,8 +208,14 @@ rr_status rr_tensor_layout(rr_tensor t, const void** data, int64_t* n_records,
                            int32_t* record_bytes, int32_t* precision);
 
 /* A bundle of rays sharing a source distance and a chi window: the rays of a
- * flat-sky map of nx by ny directions (Eqs. txty, rayid: ray id = iy*nx + ix).
- * Each wavefront of the march holds an 8 x 8 tile of the map. */
+ * flat-sky map of nx by ny directions (Sec. III E, Eqs. txty, rayid: ray id =
+ * iy*nx + ix).  Each wavefront of the march holds an 8 x 8 tile of the map.
+ * The directions are always passed explicitly; center_dir, fov_x and fov_y
+ * record the field of view they were made from (rr_fov_directions) and are
+ * checked on the host: all three zero means "not recorded"; otherwise
+ * center_dir must be a finite unit vector (| |c|^2 - 1 | <= 1e-9), each fov
+ * must lie in [0, pi), and an axis with more than one ray needs a positive
+ * fov (RR_ERR_INVALID_ARG, or RR_ERR_NONFINITE for non-finite values). */
 typedef struct {
   int64_t ray_offset;    /* index of this bundle's first ray in the output arrays */
   int64_t n_rays;        /* nx * ny; 0 is allowed (empty bundle) */
@@ -217,7 +223,30 @@ typedef struct {
   int32_t nx, ny;
   double chi_s;          /* source distance (defines g) */
   double chi_hi, chi_lo; /* this call's chi window, 0 <= chi_lo < chi_hi <= chi_s */
+  double center_dir[3];  /* unit vector of the map centre (e3 of rr_fov_directions) */
+  double fov_x, fov_y;   /* opening angles Upsilon_x, Upsilon_y of Eq. txty, radians */
 } rr_bundle;
+
+/* Ray directions of an nx by ny flat-sky map (Sec. III E).  Host only, FP64,
+ * no GPU call: fills dir_host[3 * (iy * nx + ix) + a] (0-based Eq. rayid).
+ * The angles follow Eq. txty, theta_i = fov / (N - 1) * (i - 1) - fov / 2 for
+ * i = 1..N (a single ray, N = 1, sits on the axis: theta = 0).  The paper
+ * does not say how (theta_x, theta_y) become a direction; the mapping here is
+ * the gnomonic one about the map centre: with e3 = center_dir / |center_dir|,
+ * e1 = normalise(h x e3) where h = z^ if |e3_z| < 0.9 else x^ (e1 = x^ and
+ * e2 = +-y^ when e3 lies on the z axis), e2 = e3 x e1,
+ *     d = (tan(theta_x) e1 + tan(theta_y) e2) + e3,  n = d / |d|,
+ * evaluated in that order with separate roundings (no fused multiply-add),
+ * |d| = sqrt((d_x^2 + d_y^2) + d_z^2), tan from the C library.  The same
+ * bits come from any caller that evaluates the formula in the same order.
+ *  center_dir host, 3 doubles, finite and non-zero (normalised here).
+ *  fov_x, fov_y in [0, pi) radians; positive when the axis has nx (ny) > 1.
+ *  nx, ny       1 .. 65536 each.
+ *  dir_host     host, caller-owned, nx * ny * 3 doubles, written.
+ * Returns RR_ERR_INVALID_ARG (NULL pointer, bad size or angle) or
+ * RR_ERR_NONFINITE; nothing is written then. */
+rr_status rr_fov_directions(const double center_dir[3], double fov_x, double fov_y, int32_t nx,
+                            int32_t ny, double* dir_host);
 
 typedef struct {
   double observer[3];        /* observer position in the periodic box; it and every
@@ -246,7 +275,15 @@ typedef struct {
 } rr_trace_params;
 
 /* A plan owns the work queue, the device copies of bundle tables, tuning
- * results and captured graphs.  Not thread-safe: one host thread per plan. */
+ * results and captured graphs.  Not thread-safe: one host thread per plan.
+ * A plan serves one stream at a time: its queue counter and split-march
+ * resume points are shared by every launch it makes, so calls on different
+ * streams must be ordered by the caller (an event or a synchronisation
+ * between them); the same holds for rr_trace_rays_adjoint on one tensor
+ * (its workspace).  Bundle tables (one per distinct bundle array, chi
+ * windows included) are cached up to 256; beyond that the least recently
+ * used table that the captured graph does not reference is released, after
+ * waiting for the last launch that read it. */
 rr_status rr_plan_create(rr_plan* p);
 rr_status rr_plan_destroy(rr_plan p);
 

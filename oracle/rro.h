@@ -11,9 +11,9 @@
  * step by step:
  *   centre tidal tensor      Sec. IV C, Eq. (tidalexample)
  *   AMR fallback             Sec. IV C (option 2: interpolate coarse d_a d_b Phi)
- *   vertex interpolation     Sec. III F (regular average), Eqs. (alphac3d),
+ *   vertex interpolation     Sec. III H (regular average), Eqs. (alphac3d),
  *                            (alphaf3d), hanging vertices (text after Eq. rhoV_1)
- *   ray walk                 Sec. III E 1, Eqs. (rayposition)-(disttocross)
+ *   ray walk                 Sec. III F 1, Eqs. (rayposition)-(disttocross)
  *   trilinear reconstruction Eqs. (trilinear_int), (trilinear_coef), (Deltas)
  *   d_N coefficients         App. B, Eq. (dns)
  *   per-cell lensing integral Eq. (Iclensing); NGP variant Eq. (Iclensing_ngp)
@@ -74,7 +74,7 @@ double rro_cell_integral(const double* Q, const double* p1, double h, const doub
 /* The projection of T used as the integrand (Eqs. n1n1, n2n2, n1n2). */
 double rro_projection(const double* dir, const double* T, int32_t quantity);
 
-/* Method A (Eq. kappa2, Sec. IV C): vertex fields (delta, grad Phi) from
+/* Method A (Eq. kappa2, Sec. IV D): vertex fields (delta, grad Phi) from
  * the cell values (central differences of spacing h, mean of the eight
  * incident cells); fv: n^3 x 4. */
 void rro_method_a_vertex_fields(int32_t n, int32_t open, double h, const double* phi,

@@ -4,7 +4,7 @@
  *
  * kappa is linear in Phi (straight rays, Born approximation, Sec. IV A,
  * Eq. jacobian2), so the gradient is the transpose of the forward chain
- *   Phi --(Eq. tidalexample)--> centre tensor --(vertex mean, Sec. III F)-->
+ *   Phi --(Eq. tidalexample)--> centre tensor --(vertex mean, Sec. III H)-->
  *   vertex tensor --(Eqs. n1n1+n2n2, trilinear_coef, dns, Iclensing)--> kappa.
  * Each transpose is written as the explicit scatter form of its forward map.
  * The per-cell derivative dI_c/dQ_v is the forward closed form evaluated on

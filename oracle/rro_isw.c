@@ -6,7 +6,7 @@
  *
  * Per N-body step the cell value of Q is the finite difference
  * (Phi_curr - Phi_prev) / dt of the potentials of the current and the
- * previous step; vertices take the mean of their eight cells (Sec. III F)
+ * previous step; vertices take the mean of their eight cells (Sec. III H)
  * and Q is trilinear inside a cell (Eq. trilinear_int).  The paper gives no
  * kernel K for this case: it is taken constant within a step, the caller's
  * scale factor, so each cell adds scale * int Q dchi over its piece (Eq. Ic

@@ -1,5 +1,5 @@
 /*
- * rro_method_a.c -- FP64 oracle of Method A (Sec. IV C, Eq. kappa2) on a
+ * rro_method_a.c -- FP64 oracle of Method A (Sec. IV D, Eq. kappa2) on a
  * uniform periodic (or open) grid.
  * TEST INFRASTRUCTURE ONLY (see rro.h).  Plain loops, no blocking, no fusion.
  *
@@ -10,7 +10,7 @@
  *                                                        (surface term, Eq. 2nterm)
  * The term with the time derivative of the potential is dropped, as in the
  * paper.  delta and grad Phi are interpolated to vertices like the tidal
- * tensor (Sec. III F) and trilinearly inside cells.
+ * tensor (Sec. III H) and trilinearly inside cells.
  */
 #include "rro.h"
 #include "rro_common.h"

@@ -7,7 +7,7 @@
  *    size when every stencil cell exists at level l; otherwise that component
  *    is interpolated trilinearly from the eight level-(l-1) centres around the
  *    cell centre (weights 3/4, 1/4 per axis), Sec. IV C "second approach";
- *  - vertices (Sec. III F): all incident leaves on one level -> mean of their
+ *  - vertices (Sec. III H): all incident leaves on one level -> mean of their
  *    centre values; vertex in the middle of a coarse edge / face -> mean of
  *    the 2 / 4 coarse corner vertices; otherwise the mass-redistribution
  *    weights of Eqs. (alphac3d) and (alphaf3d), where N_fv,j counts the

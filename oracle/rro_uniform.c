@@ -41,7 +41,7 @@ void rro_centre_tensor_uniform(int32_t n, int32_t open, double h, const double* 
       }
 }
 
-/* Sec. III F: a vertex shared by eight cells of one level takes the mean of
+/* Sec. III H: a vertex shared by eight cells of one level takes the mean of
  * the eight centre values.  Vertex (i,j,k) sits at the lower corner of cell
  * (i,j,k). */
 void rro_vertex_tensor_uniform(int32_t n, const double* tc, double* tv) {

@@ -35,7 +35,8 @@ class FieldDesc(C.Structure):
 class Bundle(C.Structure):
     _fields_ = [("ray_offset", C.c_int64), ("n_rays", C.c_int64), ("dir", C.c_void_p),
                 ("nx", C.c_int32), ("ny", C.c_int32), ("chi_s", C.c_double),
-                ("chi_hi", C.c_double), ("chi_lo", C.c_double)]
+                ("chi_hi", C.c_double), ("chi_lo", C.c_double),
+                ("center_dir", C.c_double * 3), ("fov_x", C.c_double), ("fov_y", C.c_double)]
 
 
 class TraceParams(C.Structure):
@@ -80,6 +81,8 @@ SIGNATURES = [
     ("rr_graph_begin", _i32, [_vp, _vp]),
     ("rr_graph_end", _i32, [_vp, _vp]),
     ("rr_graph_launch", _i32, [_vp, _vp]),
+    ("rr_fov_directions", _i32, [C.POINTER(C.c_double), C.c_double, C.c_double, _i32, _i32,
+                                 _vp]),
     ("rr_last_error", C.c_char_p, []),
     ("rr_version", _i32, []),
 ]

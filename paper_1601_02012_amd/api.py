@@ -7,6 +7,7 @@ C ABI in include/rayramses.h.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -40,6 +41,36 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def _prec(p):
     return PREC[p] if isinstance(p, str) else int(p)
+
+
+def _check_buffer(t: Optional[torch.Tensor], name: str, dtype: torch.dtype, min_numel: int,
+                  exact: bool = False) -> None:
+    """Reject a caller-supplied buffer before any launch: wrong dtype, not
+    contiguous, or fewer elements than the kernels index (ValueError)."""
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    n = t.numel()
+    if (n != min_numel) if exact else (n < min_numel):
+        raise ValueError(f"{name} holds {n} elements, needs "
+                         f"{'exactly' if exact else 'at least'} {min_numel}")
+
+
+def fov_directions(center, fov_x: float, fov_y: float, nx: int, ny: int) -> np.ndarray:
+    """rr_fov_directions: (ny*nx, 3) FP64 unit directions of a flat-sky map
+    (Eq. txty angles, gnomonic about ``center``; ray id = iy*nx + ix).  Runs
+    on the host; copy the result to the device for a RayBundle."""
+    c = (C.c_double * 3)(*[float(v) for v in center])
+    out = np.empty((int(nx) * int(ny), 3), dtype=np.float64)
+    A.check("rr_fov_directions",
+            _lib.rr_fov_directions(c, float(fov_x), float(fov_y), int(nx), int(ny),
+                                   out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 class Grid:
@@ -256,7 +287,9 @@ class Plan:
 
 @dataclass
 class RayBundle:
-    """Rays of one nx-by-ny map (device FP64 unit directions, ray id = iy*nx+ix)."""
+    """Rays of one nx-by-ny map (device FP64 unit directions, ray id = iy*nx+ix).
+    ``center_dir``, ``fov_x`` and ``fov_y`` optionally record the field of view
+    the directions were made from (checked by the library)."""
     dirs: torch.Tensor
     nx: int
     ny: int
@@ -264,13 +297,17 @@ class RayBundle:
     chi_hi: float
     chi_lo: float
     ray_offset: int = 0
+    center_dir: Optional[tuple] = None
+    fov_x: float = 0.0
+    fov_y: float = 0.0
 
     @property
     def n_rays(self):
         return self.nx * self.ny
 
     def window(self, chi_hi: float, chi_lo: float) -> "RayBundle":
-        return RayBundle(self.dirs, self.nx, self.ny, self.chi_s, chi_hi, chi_lo, self.ray_offset)
+        return RayBundle(self.dirs, self.nx, self.ny, self.chi_s, chi_hi, chi_lo, self.ray_offset,
+                         self.center_dir, self.fov_x, self.fov_y)
 
 
 def _bundle_array(bundles: Sequence[RayBundle]):
@@ -289,6 +326,13 @@ def _bundle_array(bundles: Sequence[RayBundle]):
         arr[i].chi_s = b.chi_s
         arr[i].chi_hi = b.chi_hi
         arr[i].chi_lo = b.chi_lo
+        if b.center_dir is not None:
+            c = [float(v) for v in b.center_dir]
+            r = math.sqrt((c[0] * c[0] + c[1] * c[1]) + c[2] * c[2])
+            for k in range(3):
+                arr[i].center_dir[k] = c[k] / r if r > 0.0 else c[k]
+            arr[i].fov_x = float(b.fov_x)
+            arr[i].fov_y = float(b.fov_y)
     return arr
 
 
@@ -337,6 +381,11 @@ def trace(plan: Plan, tensor: TidalTensor, bundles: Sequence[RayBundle], observe
     nr = total_rays(bundles)
     fp32 = tensor.precision == A.PREC_FP32_KAHAN
     dev = "cuda"
+    _check_buffer(kappa, "kappa", torch.float32 if fp32 else torch.float64, nr)
+    _check_buffer(kappa_comp, "kappa_comp", torch.float32, nr)
+    _check_buffer(status, "status", torch.int32, nr)
+    if kappa_comp is not None and not fp32:
+        raise ValueError("kappa_comp is only used by the FP32-Kahan precision")
     if kappa is None:
         kappa = torch.zeros(nr, dtype=torch.float32 if fp32 else torch.float64, device=dev)
     if kappa_comp is None and fp32:
@@ -384,6 +433,13 @@ def trace_sources(plan: Plan, tensor: TidalTensor, bundles: Sequence[RayBundle],
     fp32 = tensor.precision == A.PREC_FP32_KAHAN
     dev = "cuda"
     src, src_p = _src_array(chi_src)
+    if state is not None:
+        _check_buffer(state.moments, "state.moments", torch.float32 if fp32 else torch.float64,
+                      nr * (4 if fp32 else 2))
+        _check_buffer(state.pieces, "state.pieces", torch.float64, nr * len(src) * 2)
+        _check_buffer(state.status, "state.status", torch.int32, nr)
+        if state.pieces.dim() != 3 or state.pieces.shape[1:] != (len(src), 2):
+            raise ValueError("state.pieces must have shape (n_rays, n_src, 2)")
     if state is None:
         mom = torch.zeros((nr, 4) if fp32 else (nr, 2),
                           dtype=torch.float32 if fp32 else torch.float64, device=dev)
@@ -408,6 +464,10 @@ def kappa_from_pieces(plan: Plan, tensor: TidalTensor, chi_src, state: SourcesOu
     """rr_kappa_from_pieces: (n_rays, n_src) FP64 kappa of every source."""
     src, src_p = _src_array(chi_src)
     nr = state.moments.shape[0]
+    fp32 = tensor.precision == A.PREC_FP32_KAHAN
+    _check_buffer(state.moments, "state.moments", torch.float32 if fp32 else torch.float64,
+                  nr * (4 if fp32 else 2), exact=True)
+    _check_buffer(state.pieces, "state.pieces", torch.float64, nr * len(src) * 2)
     out = torch.empty((nr, len(src)), dtype=torch.float64, device=state.moments.device)
     A.check("rr_kappa_from_pieces",
             _lib.rr_kappa_from_pieces(plan.handle, tensor.handle, src_p, len(src), nr,
@@ -425,6 +485,10 @@ def trace_adjoint(plan: Plan, tensor: TidalTensor, grid: Grid, bundles: Sequence
                   observer, dl_dkappa: torch.Tensor, *, dl_dphi: Optional[torch.Tensor] = None,
                   kappa_scale: float = 1.0, stream=None) -> torch.Tensor:
     """rr_trace_rays_adjoint: dL/dPhi (added to ``dl_dphi``, allocated if None)."""
+    nr = total_rays(bundles)
+    if not isinstance(dl_dkappa, torch.Tensor) or dl_dkappa.numel() < nr:
+        raise ValueError(f"dl_dkappa must be a tensor of at least {nr} elements")
+    _check_buffer(dl_dphi, "dl_dphi", torch.float32, grid.n ** 3, exact=True)
     if dl_dphi is None:
         dl_dphi = torch.zeros_like(grid.values, dtype=torch.float32)
     tp = _params(observer, tensor.precision, "kappa", kappa_scale, 0)

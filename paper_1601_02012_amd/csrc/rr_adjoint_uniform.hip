@@ -3,7 +3,7 @@
 //
 // kappa is linear in Phi (straight rays, Born approximation, Sec. IV A), so
 // dL/dPhi = A^T w for the forward chain A = (per-cell integrals) o (vertex
-// mean, Sec. III F) o (finite differences, Eq. tidalexample):
+// mean, Sec. III H) o (finite differences, Eq. tidalexample):
 //   1. scatter: re-walk every ray; the integral over one cell is
 //      sum_v omega_v Q_v with Q_v = P . T_v, so the cell adds
 //      w * scale * omega_v * P_ab to Lambda_v,ab = dL/dT_v,ab.  A corner's

@@ -34,6 +34,14 @@ rr_status hip_fail(hipError_t e, const char* what) {
   return fail(RR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+}  // namespace
+
+namespace rr {
+rr_status fov_fail(rr_status s, const char* what) { return fail(s, "%s", what); }
+}  // namespace rr
+
+namespace {
+
 #define RR_HIP(call, what)                   \
   do {                                       \
     hipError_t _e = (call);                  \
@@ -69,7 +77,14 @@ struct CachedTable {
   int32_t persistent_order = 0;
   rr::DevBundle* dev = nullptr;
   int64_t n_tiles = 0;
+  uint64_t last_use = 0;       // plan clock at the last call that used it
+  hipEvent_t used = nullptr;   // recorded after the last launch that read it
+  bool captured = false;       // used by the capture in progress
+  bool in_graph = false;       // read by the plan's instantiated graph
 };
+
+// Tables a plan keeps before it releases the least recently used one.
+constexpr size_t kMaxTables = 256;
 
 // A source-distance list (many-source walk) on the device, base-cell units.
 struct CachedSources {
@@ -103,6 +118,7 @@ struct rr_plan_s {
   std::vector<CachedSources> sources;
   double* resume = nullptr;   // per ray: where the next pass of a split march starts
   int64_t resume_cap = 0;
+  uint64_t clock = 0;         // counts get_table calls (least-recently-used order)
 };
 
 namespace {
@@ -152,7 +168,7 @@ rr_status validate_field(const rr_field_desc* f) {
 extern "C" {
 
 const char* rr_last_error(void) { return g_err.c_str(); }
-int32_t rr_version(void) { return 10000; }
+int32_t rr_version(void) { return 10100; }
 
 rr_status rr_tensor_create(const rr_field_desc* f, rr_precision p, rr_tensor* out) {
   if (!out) return fail(RR_ERR_INVALID_ARG, "out is NULL");
@@ -351,8 +367,11 @@ rr_status rr_plan_destroy(rr_plan p) {
   if (!p) return RR_OK;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
-  for (auto& c : p->tables)
+  for (auto& c : p->tables) {
+    if (c.used) (void)hipEventSynchronize(c.used);
     if (c.dev) (void)hipFree(c.dev);
+    if (c.used) (void)hipEventDestroy(c.used);
+  }
   for (auto& c : p->sources)
     if (c.dev) (void)hipFree(c.dev);
   if (p->resume) (void)hipFree(p->resume);
@@ -369,7 +388,29 @@ bool capturing(hipStream_t s) {
   return cs != hipStreamCaptureStatusNone;
 }
 
+// The field-of-view record of a bundle (Sec. III E, Eq. txty): all zero =
+// not recorded; otherwise a finite unit centre, angles in [0, pi), and a
+// positive angle on every axis that holds more than one ray.
+rr_status validate_fov(const rr_bundle& x, int32_t i) {
+  const double* c = x.center_dir;
+  if (c[0] == 0.0 && c[1] == 0.0 && c[2] == 0.0 && x.fov_x == 0.0 && x.fov_y == 0.0)
+    return RR_OK;
+  if (!finite3(c) || !std::isfinite(x.fov_x) || !std::isfinite(x.fov_y))
+    return fail(RR_ERR_NONFINITE, "bundle %d: field-of-view record is not finite", i);
+  const double c2 = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2];
+  if (!(std::fabs(c2 - 1.0) <= 1e-9))
+    return fail(RR_ERR_INVALID_ARG, "bundle %d: center_dir is not a unit vector", i);
+  if (!(x.fov_x >= 0.0 && x.fov_x < M_PI) || !(x.fov_y >= 0.0 && x.fov_y < M_PI))
+    return fail(RR_ERR_INVALID_ARG, "bundle %d: fields of view must lie in [0, pi)", i);
+  if ((x.nx > 1 && !(x.fov_x > 0.0)) || (x.ny > 1 && !(x.fov_y > 0.0)))
+    return fail(RR_ERR_INVALID_ARG,
+                "bundle %d: a %d x %d map needs a positive fov on every axis with several rays",
+                i, x.nx, x.ny);
+  return RR_OK;
+}
+
 rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle* b, int32_t nb) {
+  rr_status st = RR_OK;
   if (!t) return fail(RR_ERR_INVALID_ARG, "tensor is NULL");
   if (!tp) return fail(RR_ERR_INVALID_ARG, "trace params are NULL");
   if (nb < 0 || (nb > 0 && !b)) return fail(RR_ERR_INVALID_ARG, "bad bundle array");
@@ -422,6 +463,8 @@ rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle
                   (long long)x.n_rays);
     if (!std::isfinite(x.chi_s) || !std::isfinite(x.chi_hi) || !std::isfinite(x.chi_lo))
       return fail(RR_ERR_NONFINITE, "bundle %d: chi values must be finite", i);
+    st = validate_fov(x, i);
+    if (st != RR_OK) return st;
     if (!(x.chi_s > 0.0)) return fail(RR_ERR_INVALID_ARG, "bundle %d: chi_s must be > 0", i);
     if (!(0.0 <= x.chi_lo && x.chi_lo < x.chi_hi && x.chi_hi <= x.chi_s))
       return fail(RR_ERR_INVALID_ARG,
@@ -436,22 +479,52 @@ rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle
   return RR_OK;
 }
 
+// Release the least recently used bundle table that no graph reads, after
+// the last launch that read it has finished.
+rr_status evict_table(rr_plan p) {
+  auto victim = p->tables.end();
+  for (auto it = p->tables.begin(); it != p->tables.end(); ++it)
+    if (!it->in_graph && !it->captured &&
+        (victim == p->tables.end() || it->last_use < victim->last_use))
+      victim = it;
+  if (victim == p->tables.end())
+    return fail(RR_ERR_CAPACITY, "all %zu bundle tables of the plan are held by its graph",
+                p->tables.size());
+  RR_HIP(hipEventSynchronize(victim->used), "bundle table release (wait)");
+  RR_HIP(hipFree(victim->dev), "bundle table release");
+  (void)hipEventDestroy(victim->used);
+  p->tables.erase(victim);
+  return RR_OK;
+}
+
+// After the launches of a call: the table's event marks its last reader
+// (inside a capture the graph holds the table instead).
+rr_status table_used(CachedTable* c, hipStream_t s) {
+  if (!capturing(s)) RR_HIP(hipEventRecord(c->used, s), "bundle table event");
+  return RR_OK;
+}
+
 // Find or upload the device bundle table for (bundles, grid unit).
 rr_status get_table(rr_plan p, rr_tensor t, const rr_bundle* b, int32_t nb, int persistent,
-                    hipStream_t s, const CachedTable** out) {
+                    hipStream_t s, CachedTable** out) {
+  const bool cap = capturing(s);
   for (auto& c : p->tables) {
     if (c.n == t->n && c.box == t->box && c.persistent_order == persistent &&
         (int32_t)c.key.size() == nb &&
         (nb == 0 || std::memcmp(c.key.data(), b, sizeof(rr_bundle) * nb) == 0)) {
+      c.last_use = ++p->clock;
+      c.captured |= cap;
       *out = &c;
       return RR_OK;
     }
   }
-  if (capturing(s))
+  if (cap)
     return fail(RR_ERR_CAPACITY,
                 "bundle table not uploaded before graph capture: run the call once first");
-  if (p->tables.size() >= 256)
-    return fail(RR_ERR_CAPACITY, "plan holds 256 bundle tables already");
+  if (p->tables.size() >= kMaxTables) {
+    rr_status st = evict_table(p);
+    if (st != RR_OK) return st;
+  }
   const double h0 = t->box / (double)t->n;
   std::vector<int32_t> order(nb);
   for (int32_t i = 0; i < nb; ++i) order[i] = i;
@@ -485,11 +558,19 @@ rr_status get_table(rr_plan p, rr_tensor t, const rr_bundle* b, int32_t nb, int 
   c.box = t->box;
   c.persistent_order = persistent;
   c.n_tiles = tiles;
+  c.last_use = ++p->clock;
+  RR_HIP(hipEventCreateWithFlags(&c.used, hipEventDisableTiming), "bundle table event");
   hipError_t e = hipMalloc((void**)&c.dev, sizeof(rr::DevBundle) * host.size());
-  if (e != hipSuccess) return fail(RR_ERR_OOM, "bundle table: %s", hipGetErrorString(e));
-  RR_HIP(hipMemcpy(c.dev, host.data(), sizeof(rr::DevBundle) * host.size(),
-                   hipMemcpyHostToDevice),
-         "bundle table upload");
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(c.used);
+    return fail(RR_ERR_OOM, "bundle table: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(c.dev, host.data(), sizeof(rr::DevBundle) * host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(c.dev);
+    (void)hipEventDestroy(c.used);
+    return hip_fail(e, "bundle table upload");
+  }
   p->tables.push_back(std::move(c));
   *out = &p->tables.back();
   return RR_OK;
@@ -655,7 +736,7 @@ rr_status rr_rays_vertex_box(rr_plan p, rr_tensor t, const rr_trace_params* tp,
   if (t->kind != RR_GRID_UNIFORM) return fail(RR_ERR_UNSUPPORTED, "box builds are for uniform grids");
   const hipStream_t hs = (hipStream_t)s;
   if (capturing(hs)) return fail(RR_ERR_CAPACITY, "the ray box is computed outside captures");
-  const CachedTable* tab = nullptr;
+  CachedTable* tab = nullptr;
   st = get_table(p, t, bundles, n_bundles, 0, hs, &tab);
   if (st != RR_OK) return st;
   int* dev = reinterpret_cast<int*>(reinterpret_cast<char*>(p->queue) + 64);
@@ -669,6 +750,8 @@ rr_status rr_rays_vertex_box(rr_plan p, rr_tensor t, const rr_trace_params* tp,
   for (int k = 0; k < 3; ++k) a.o[k] = tp->observer[k] / h0;
   a.n = t->n;
   RR_HIP(rr::launch_ray_bounds(a, dev, hs), "ray bounds launch");
+  st = table_used(tab, hs);
+  if (st != RR_OK) return st;
   RR_HIP(hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, hs), "bounds read");
   RR_HIP(hipStreamSynchronize(hs), "bounds sync");
   const int n = t->n;
@@ -823,7 +906,7 @@ rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const 
                        hipStream_t hs, int persistent, int block, int waves_per_cu,
                        const double* src, int32_t n_src, double* pieces, int passes) {
   rr_status st;
-  const CachedTable* tab = nullptr;
+  CachedTable* tab = nullptr;
   st = get_table(p, t, bundles, n_bundles, persistent, hs, &tab);
   if (st != RR_OK) return st;
   if (tab->n_tiles == 0) return RR_OK;
@@ -912,7 +995,7 @@ rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const 
       RR_HIP(t->oct->march(a, persistent, grid_waves, hs), "octree march launch");
     }
   }
-  return RR_OK;
+  return table_used(tab, hs);
 }
 
 }  // namespace
@@ -942,7 +1025,7 @@ rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
   if (f->n_base != t->n) return fail(RR_ERR_INVALID_ARG, "field and tensor grids differ");
   if (!dl_dkappa || !dl_dphi) return fail(RR_ERR_INVALID_ARG, "gradient pointers are NULL");
   const hipStream_t hs = (hipStream_t)s;
-  const CachedTable* tab = nullptr;
+  CachedTable* tab = nullptr;
   st = get_table(p, t, bundles, n_bundles, 0, hs, &tab);
   if (st != RR_OK) return st;
   const int64_t nv = (int64_t)t->n * t->n * t->n;
@@ -963,13 +1046,14 @@ rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
   a.quantity = RR_Q_KAPPA;
   a.max_crossings = tp->max_crossings;
   RR_HIP(rr::launch_adjoint_uniform(a, dl_dkappa, (float*)t->grad, dl_dphi, hs), "adjoint launch");
-  return RR_OK;
+  return table_used(tab, hs);
 }
 
 rr_status rr_graph_begin(rr_plan p, rr_stream s) {
   if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
   if (!s) return fail(RR_ERR_INVALID_ARG, "graph capture needs a non-default stream");
   if (capturing((hipStream_t)s)) return fail(RR_ERR_CAPACITY, "stream is already capturing");
+  for (auto& c : p->tables) c.captured = false;
   RR_HIP(hipStreamBeginCapture((hipStream_t)s, hipStreamCaptureModeThreadLocal), "begin capture");
   return RR_OK;
 }
@@ -982,6 +1066,11 @@ rr_status rr_graph_end(rr_plan p, rr_stream s) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = g;
+  // the new graph holds exactly the tables its capture used
+  for (auto& c : p->tables) {
+    c.in_graph = c.captured;
+    c.captured = false;
+  }
   RR_HIP(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0), "graph instantiate");
   return RR_OK;
 }
@@ -990,6 +1079,9 @@ rr_status rr_graph_launch(rr_plan p, rr_stream s) {
   if (!p) return fail(RR_ERR_INVALID_ARG, "plan is NULL");
   if (!p->exec) return fail(RR_ERR_INVALID_ARG, "no graph captured on this plan");
   RR_HIP(hipGraphLaunch(p->exec, (hipStream_t)s), "graph launch");
+  // the graph's tables are released only after this replay has finished
+  for (auto& c : p->tables)
+    if (c.in_graph) RR_HIP(hipEventRecord(c.used, (hipStream_t)s), "bundle table event");
   return RR_OK;
 }
 

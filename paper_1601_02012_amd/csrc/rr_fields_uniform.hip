@@ -1,5 +1,5 @@
 // rr_fields_uniform.hip -- the other vertex fields of a uniform grid, each the
-// mean over the eight cells incident on a vertex (Sec. III F, regular
+// mean over the eight cells incident on a vertex (Sec. III H, regular
 // vertices):
 //   Method A (Eq. kappa2): c delta and the central-difference gradient of Phi;
 //   ISW (Sec. VII): the rate (Phi_curr - Phi_prev) / dt of consecutive steps.

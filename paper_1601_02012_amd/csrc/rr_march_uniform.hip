@@ -1,5 +1,5 @@
 // rr_march_uniform.hip -- cell-by-cell ray march through a uniform grid
-// (Sec. III E, Eqs. rayposition - disttocross) with the per-cell lensing
+// (Sec. III F, Eqs. rayposition - disttocross) with the per-cell lensing
 // integral of the trilinear vertex reconstruction (Eqs. trilinear_int,
 // Iclensing) and its accumulation along the ray (Eq. sumIc).
 //

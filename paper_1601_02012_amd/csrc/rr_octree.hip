@@ -6,7 +6,7 @@
 // integer coordinates I at that level; locating a level-l position walks the
 // child_oct links down from its base cell (at most four loads).
 //
-// Build (Sec. IV C, Sec. III F):
+// Build (Sec. IV C, Sec. III H):
 //  1. centre tensor, level by level: each component uses the level's own
 //     finite-difference stencil (Eq. tidalexample, h = 2^-l) when every
 //     stencil cell exists at level l; otherwise it is the trilinear
@@ -19,7 +19,7 @@
 //     boundary takes the mass-redistribution weights of Eqs. (alphac3d) and
 //     (alphaf3d), N_fv,j being the number of corners of fine leaf j that
 //     touch a coarse leaf.
-// March (Sec. III E): the uniform crossing rule on the current leaf's level;
+// March (Sec. III F): the uniform crossing rule on the current leaf's level;
 // past a face, a coarser neighbour is entered by halving the coordinates, a
 // refined one by descending to the child next to the crossed face (slab rule
 // on the other axes).

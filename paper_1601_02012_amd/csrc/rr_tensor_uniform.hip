@@ -1,5 +1,5 @@
 // rr_tensor_uniform.hip -- tidal tensor at cell centres (Eq. tidalexample) fused
-// with its interpolation to cell vertices (Sec. III F, regular vertices).
+// with its interpolation to cell vertices (Sec. III H, regular vertices).
 //
 // Vertex (i,j,k) is the lower corner of cell (i,j,k) and takes the mean of the
 // centre tensors of cells {i-1,i} x {j-1,j} x {k-1,k}.  Summing the centre

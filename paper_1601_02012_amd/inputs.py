@@ -7,7 +7,7 @@ per-cell integral), so both the HIP path and the FP64 oracle can consume its
 arrays without sharing any of the method's code.
 
 Paper references (RAY-RAMSES, arXiv:1601.02012):
-  * ray angular grid: Sec. III C, Eq. (txty); ray ids: Eq. (rayid);
+  * ray angular grid: Sec. III E, Eq. (txty); ray ids: Eq. (rayid);
   * comoving distance chi(z) = c int dz/H(z): Sec. III B, below Eq. (raypos);
   * cosmology of the lensing runs (Omega_b, Omega_c, h): Sec. VI A;
   * Gaussian test potential: Sec. V, Eq. (gaussian);
@@ -88,17 +88,22 @@ def fov_angles(fov: float, n: int) -> np.ndarray:
 
 
 def _basis(center):
-    e3 = np.asarray(center, dtype=np.float64)
-    e3 = e3 / math.sqrt(float(e3 @ e3))
-    helper = np.array([0.0, 0.0, 1.0]) if abs(e3[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
-    if abs(e3[0]) < 1e-300 and abs(e3[1]) < 1e-300:
-        e1, e2 = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
-        if e3[2] < 0:
-            e2 = -e2
-        return e1, e2, e3
-    e1 = np.cross(helper, e3)
-    e1 /= math.sqrt(float(e1 @ e1))
-    e2 = np.cross(e3, e1)
+    """Frame (e1, e2, e3) of a map centred on ``center`` (gnomonic reading of
+    Eq. txty): e3 the unit centre, e1 = normalise(h x e3) with h = z^ unless
+    e3 is within ~26 deg of the z axis (then h = x^), e2 = e3 x e1; on the z
+    axis itself e1 = x^ and e2 = +-y^.  Plain float arithmetic in a fixed
+    order (no dot-product library call), one rounding per operation."""
+    c0, c1, c2 = (float(v) for v in center)
+    r = math.sqrt((c0 * c0 + c1 * c1) + c2 * c2)
+    e3 = (c0 / r, c1 / r, c2 / r)
+    if e3[0] == 0.0 and e3[1] == 0.0:
+        return (1.0, 0.0, 0.0), (0.0, -1.0 if e3[2] < 0.0 else 1.0, 0.0), e3
+    h = (0.0, 0.0, 1.0) if abs(e3[2]) < 0.9 else (1.0, 0.0, 0.0)
+    u = (h[1] * e3[2] - h[2] * e3[1], h[2] * e3[0] - h[0] * e3[2], h[0] * e3[1] - h[1] * e3[0])
+    ru = math.sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2])
+    e1 = (u[0] / ru, u[1] / ru, u[2] / ru)
+    e2 = (e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2],
+          e3[0] * e1[1] - e3[1] * e1[0])
     return e1, e2, e3
 
 
@@ -106,14 +111,16 @@ def fov_directions(center, fov_x: float, fov_y: float, nx: int, ny: int) -> np.n
     """Unit ray directions (observer -> source), shape (ny*nx, 3), FP64.
 
     Flat-sky gnomonic mapping of the Eq. (txty) angles about ``center``;
-    row-major by ray id, ray id = iy*nx + ix (0-based Eq. (rayid))."""
-    tx = np.tan(fov_angles(fov_x, nx))
-    ty = np.tan(fov_angles(fov_y, ny))
-    e1, e2, e3 = _basis(center)
+    row-major by ray id, ray id = iy*nx + ix (0-based Eq. (rayid)):
+    d = (tan(theta_x) e1 + tan(theta_y) e2) + e3, n = d / sqrt((d_x^2 + d_y^2)
+    + d_z^2), every operation rounded on its own, tan from the C library."""
+    tx = np.array([math.tan(a) for a in fov_angles(fov_x, nx)])
+    ty = np.array([math.tan(a) for a in fov_angles(fov_y, ny)])
+    e1, e2, e3 = (np.array(v) for v in _basis(center))
     d = (tx[None, :, None] * e1[None, None, :] + ty[:, None, None] * e2[None, None, :]
          + e3[None, None, :])
     d = d.reshape(-1, 3)
-    norm = np.sqrt(np.sum(d * d, axis=1))
+    norm = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
     return np.ascontiguousarray(d / norm[:, None])
 
 

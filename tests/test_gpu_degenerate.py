@@ -1,4 +1,4 @@
-"""GPU parity on the degenerate cases of the crossing rule (Sec. III E):
+"""GPU parity on the degenerate cases of the crossing rule (Sec. III F):
 rays along a lattice axis or in a lattice plane (a direction component of
 exactly zero), rays through lattice edges and vertices (two or three planes
 at one parameter), observers on lattice planes and vertices, windows ending

@@ -1,4 +1,4 @@
-"""Seeded stress of the crossing rule's tie handling (Sec. III E): random
+"""Seeded stress of the crossing rule's tie handling (Sec. III F): random
 2:1-balanced octrees of two and three levels and uniform grids, observers on
 lattice points of the finer levels (multiples of 1/4 base cell), directions
 mixing exact axis, face-diagonal and body-diagonal ones with random ones,

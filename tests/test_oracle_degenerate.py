@@ -1,5 +1,5 @@
 """Pins of the oracle's walk on the degenerate cases of the crossing rule
-(Sec. III E, Eqs. disttocross, rayposition): rays along a lattice axis or in
+(Sec. III F, Eqs. disttocross, rayposition): rays along a lattice axis or in
 a lattice plane (a direction component exactly zero: that axis is never
 crossed), rays through lattice edges and vertices (two or three planes at the
 same parameter: every tied axis steps at once), observers on lattice planes

@@ -1,4 +1,4 @@
-"""Octree pins of the FP64 oracle (Sec. III F, Sec. IV C of the paper)."""
+"""Octree pins of the FP64 oracle (Sec. III H, Sec. IV C of the paper)."""
 import math
 
 import numpy as np
@@ -31,7 +31,7 @@ def test_P8_weight_examples(oracle, dim, nc, nfv, ac, af):
 def test_P8_seven_coarse_one_fine_in_a_tree(oracle):
     """One refined base cell: its outer corner is shared by 7 coarse leaves and
     1 fine leaf with N_fv = 7, so the vertex gets 8/63 per coarse centre and
-    1/9 for the fine one (the 3D example in Sec. III F)."""
+    1/9 for the fine one (the 3D example in Sec. III H)."""
     n = 4
     target = (1, 1, 1)
     t = I.build_octree(n, 1, lambda l, c: np.all(c == np.array(target), axis=1))
@@ -58,7 +58,7 @@ def test_P8_seven_coarse_one_fine_in_a_tree(oracle):
 # --------------------------------------------------------------------- P7 --
 @pytest.mark.parametrize("seed,levels,p", [(0, 2, 0.2), (1, 3, 0.15), (2, 4, 0.08), (3, 3, 0.5)])
 def test_P7_vertex_interpolation_conserves_mass(oracle, seed, levels, p):
-    """Sec. III F: the total 'mass' from cell centres equals the total from the
+    """Sec. III H: the total 'mass' from cell centres equals the total from the
     vertex reconstruction, on random 2:1-balanced octrees."""
     rng = np.random.default_rng(seed)
     t = I.random_octree(6, levels, p, rng)
@@ -210,7 +210,7 @@ def test_P2_quadratic_shear_on_octree(oracle):
 
 def test_P8_face_centre_hanging_vertex(oracle):
     """A vertex in the middle of a coarse face takes the mean of the face's
-    four coarse corner values (Sec. III F, text after Eq. rhoV_1)."""
+    four coarse corner values (Sec. III H, text after Eq. rhoV_1)."""
     n = 4
     t = I.build_octree(n, 1, lambda l, c: np.all(c == np.array([1, 1, 1]), axis=1))
     ot = _otree(oracle, t)

@@ -1,4 +1,4 @@
-"""Pin of the oracle's octree walk (Sec. III E on the levels of Sec. III A)
+"""Pin of the oracle's octree walk (Sec. III F on the levels of Sec. III A)
 against a point-location walker written independently of it: at the start of
 every piece the walker finds the leaf holding the ray by descending from the
 base cell, applying the slab rule on every level (a point on a plane belongs
