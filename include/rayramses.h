@@ -406,6 +406,26 @@ rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
                                 int32_t n_bundles, const float* dl_dkappa, float* dl_dphi,
                                 rr_stream s);
 
+/* rr_trace_rays for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and results as rr_trace_rays, without a plan: the bundle
+ * table and the persistent queue counter live in a fixed device array of the
+ * library (72.5 KiB per GPU, held until the process ends; its address is
+ * resolved once per device), written by kernels on s before the march.
+ *  - n_bundles <= 1024, else RR_ERR_CAPACITY (nothing enqueued).
+ *  - tp->persistent: 1 = persistent workgroups (16 wavefronts per compute
+ *    unit) fed by the queue counter; 0 or -1 = one wavefront per 8x8 tile
+ *    (256-thread workgroups).  The march is never split into passes.
+ *  - No hipMalloc, hipFree or other allocating call; host memory is the
+ *    stack only.
+ *  - Every call on one GPU shares that GPU's array, which keeps the last
+ *    call's table: calls on one stream are ordered, but calls that overlap
+ *    on one GPU (other streams or host threads) race and must be ordered by
+ *    the caller. */
+rr_status rr_trace_rays_noalloc(rr_tensor t, const rr_trace_params* tp,
+                                const rr_bundle* bundles /* host */, int32_t n_bundles,
+                                void* kappa, float* kappa_comp, int32_t* ray_status, rr_stream s);
+
 /* Capture every library call enqueued on s between begin and end into one
  * HIP graph owned by the plan (replaces any previous one), then replay it
  * with rr_graph_launch.  Bundle tables must have been uploaded before begin.

@@ -66,6 +66,8 @@ SIGNATURES = [
     ("rr_plan_destroy", _i32, [_vp]),
     ("rr_trace_rays", _i32, [_vp, _vp, C.POINTER(TraceParams), C.POINTER(Bundle), _i32, _vp, _vp,
                              _vp, _vp]),
+    ("rr_trace_rays_noalloc", _i32, [_vp, C.POINTER(TraceParams), C.POINTER(Bundle), _i32, _vp,
+                                     _vp, _vp, _vp]),
     ("rr_trace_rays_sources", _i32, [_vp, _vp, C.POINTER(TraceParams), C.POINTER(Bundle), _i32,
                                      C.POINTER(C.c_double), _i32, _vp, _vp, _vp, _vp]),
     ("rr_kappa_from_pieces", _i32, [_vp, _vp, C.POINTER(C.c_double), _i32, _i64, _vp, _vp, _vp,

@@ -408,6 +408,35 @@ def trace(plan: Plan, tensor: TidalTensor, bundles: Sequence[RayBundle], observe
     return TraceOutput(kappa, kappa_comp, status, hsh, cnt, log)
 
 
+def trace_noalloc(tensor: TidalTensor, bundles: Sequence[RayBundle], observer, *,
+                  kappa: torch.Tensor, kappa_comp: Optional[torch.Tensor] = None,
+                  status: Optional[torch.Tensor] = None, kappa_scale: float = 1.0,
+                  quantity="kappa", persistent: int = 0, max_crossings: int = 0,
+                  hash: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None,
+                  integral: str = "trilinear", stream=None) -> TraceOutput:
+    """rr_trace_rays_noalloc: rr_trace_rays without a plan and without any
+    device allocation (the caller passes every output buffer)."""
+    nr = total_rays(bundles)
+    fp32 = tensor.precision == A.PREC_FP32_KAHAN
+    if kappa is None:
+        raise ValueError("trace_noalloc needs the caller's kappa buffer")
+    _check_buffer(kappa, "kappa", torch.float32 if fp32 else torch.float64, nr)
+    _check_buffer(kappa_comp, "kappa_comp", torch.float32, nr)
+    _check_buffer(status, "status", torch.int32, nr)
+    _check_buffer(hash, "hash", torch.int64, nr)
+    _check_buffer(count, "count", torch.int64, nr)
+    if kappa_comp is not None and not fp32:
+        raise ValueError("kappa_comp is only used by the FP32-Kahan precision")
+    tp = _params(observer, tensor.precision, quantity, kappa_scale, persistent, max_crossings,
+                 hash, count, None, 0, integral)
+    arr = _bundle_array(bundles)
+    A.check("rr_trace_rays_noalloc",
+            _lib.rr_trace_rays_noalloc(tensor.handle, C.byref(tp), arr, len(bundles),
+                                       _ptr(kappa), _ptr(kappa_comp), _ptr(status),
+                                       _stream(stream)))
+    return TraceOutput(kappa, kappa_comp, status, hash, count)
+
+
 class SourcesOutput:
     """State of the many-source walk: per-ray moments (FP32 Kahan pairs
     {A, A_comp, B, B_comp} or FP64 {A, B}), pieces (n_rays, n_src, 2) FP64,

@@ -479,6 +479,38 @@ rr_status validate_trace(rr_tensor t, const rr_trace_params* tp, const rr_bundle
   return RR_OK;
 }
 
+// Launch order of the bundles: as given, or (persistent launches)
+// longest-processing-time first, the chi window setting the steps per ray.
+// A stable insertion sort on the caller's index array (no allocation).
+void launch_order(const rr_bundle* b, int32_t nb, int persistent, int32_t* order) {
+  for (int32_t i = 0; i < nb; ++i) order[i] = i;
+  if (!persistent) return;
+  for (int32_t i = 1; i < nb; ++i) {
+    const int32_t v = order[i];
+    const double len = b[v].chi_hi - b[v].chi_lo;
+    int32_t j = i - 1;
+    for (; j >= 0 && (b[order[j]].chi_hi - b[order[j]].chi_lo) < len; --j) order[j + 1] = order[j];
+    order[j + 1] = v;
+  }
+}
+
+// One bundle-table entry in base-cell units; returns the tile count after it.
+int64_t table_entry(rr_tensor t, const rr_bundle& x, int64_t tiles, rr::DevBundle* d) {
+  const double h0 = t->box / (double)t->n;
+  d->dir = x.dir;
+  d->ray_offset = x.ray_offset;
+  d->n_rays = x.n_rays;
+  d->nx = x.n_rays ? x.nx : 0;
+  d->ny = x.n_rays ? x.ny : 0;
+  d->tiles_x = (d->nx + 7) / 8;
+  d->tiles_y = (d->ny + 7) / 8;
+  d->tile_begin = tiles;
+  d->chi_s = x.chi_s / h0;
+  d->chi_hi = x.chi_hi / h0;
+  d->chi_lo = x.chi_lo / h0;
+  return tiles + (int64_t)d->tiles_x * d->tiles_y;
+}
+
 // Release the least recently used bundle table that no graph reads, after
 // the last launch that read it has finished.
 rr_status evict_table(rr_plan p) {
@@ -525,33 +557,11 @@ rr_status get_table(rr_plan p, rr_tensor t, const rr_bundle* b, int32_t nb, int 
     rr_status st = evict_table(p);
     if (st != RR_OK) return st;
   }
-  const double h0 = t->box / (double)t->n;
   std::vector<int32_t> order(nb);
-  for (int32_t i = 0; i < nb; ++i) order[i] = i;
-  if (persistent) {
-    // longest-processing-time first: the chi window sets the steps per ray
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-      return (b[x].chi_hi - b[x].chi_lo) > (b[y].chi_hi - b[y].chi_lo);
-    });
-  }
+  launch_order(b, nb, persistent, order.data());
   std::vector<rr::DevBundle> host(std::max(nb, 1));
   int64_t tiles = 0;
-  for (int32_t k = 0; k < nb; ++k) {
-    const rr_bundle& x = b[order[k]];
-    rr::DevBundle& d = host[k];
-    d.dir = x.dir;
-    d.ray_offset = x.ray_offset;
-    d.n_rays = x.n_rays;
-    d.nx = x.n_rays ? x.nx : 0;
-    d.ny = x.n_rays ? x.ny : 0;
-    d.tiles_x = (d.nx + 7) / 8;
-    d.tiles_y = (d.ny + 7) / 8;
-    d.tile_begin = tiles;
-    d.chi_s = x.chi_s / h0;
-    d.chi_hi = x.chi_hi / h0;
-    d.chi_lo = x.chi_lo / h0;
-    tiles += (int64_t)d.tiles_x * d.tiles_y;
-  }
+  for (int32_t k = 0; k < nb; ++k) tiles = table_entry(t, b[order[k]], tiles, &host[k]);
   CachedTable c;
   c.key.assign(b, b + nb);
   c.n = t->n;
@@ -901,6 +911,34 @@ rr_status rr_plan_tuned_shape(rr_plan p, const rr_bundle* bundles, int32_t n_bun
 
 namespace {
 
+// Everything a march launch takes from the tensor, the trace parameters and
+// the outputs (the bundle table, queue and pass state are set by the caller).
+void march_args(rr_tensor t, const rr_trace_params* tp, void* kappa, float* kappa_comp,
+                int32_t* ray_status, rr::TraceArgs* a) {
+  const double h0 = t->box / (double)t->n;
+  for (int k = 0; k < 3; ++k) a->o[k] = tp->observer[k] / h0;
+  a->kappa_scale = tp->kappa_scale;
+  a->n = t->n;
+  a->open = t->boundary == RR_BOUNDARY_OPEN;
+  a->quantity = tp->quantity;
+  a->integral = tp->integral;
+  a->mode = t->method_a ? 2 : (tp->integral == RR_INTEGRAL_NGP ? 1 : 0);
+  if (t->isw) {
+    // int Q dchi~ in base-cell units times h0: the integral in box units
+    a->mode = 4;
+    a->kappa_scale = tp->kappa_scale * h0;
+  }
+  a->max_crossings = tp->max_crossings;
+  a->kappa = kappa;
+  a->kappa_comp = kappa_comp;
+  a->status = ray_status;
+  a->hash = tp->crossing_hash;
+  a->count = tp->crossing_count;
+  a->log = tp->crossing_log;
+  a->log_stride = tp->log_stride;
+  a->pause_chi = -INFINITY;
+}
+
 rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
                        int32_t n_bundles, void* kappa, float* kappa_comp, int32_t* ray_status,
                        hipStream_t hs, int persistent, int block, int waves_per_cu,
@@ -912,36 +950,17 @@ rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const 
   if (tab->n_tiles == 0) return RR_OK;
 
   rr::TraceArgs a{};
+  march_args(t, tp, kappa, kappa_comp, ray_status, &a);
   a.bundles = tab->dev;
   a.n_bundles = n_bundles;
   a.n_tiles = tab->n_tiles;
   const double h0 = t->box / (double)t->n;
-  for (int k = 0; k < 3; ++k) a.o[k] = tp->observer[k] / h0;
-  a.kappa_scale = tp->kappa_scale;
-  a.n = t->n;
-  a.open = t->boundary == RR_BOUNDARY_OPEN;
-  a.quantity = tp->quantity;
-  a.integral = tp->integral;
-  a.mode = t->method_a ? 2 : (tp->integral == RR_INTEGRAL_NGP ? 1 : 0);
-  if (t->isw) {
-    // int Q dchi~ in base-cell units times h0: the integral in box units
-    a.mode = 4;
-    a.kappa_scale = tp->kappa_scale * h0;
-  }
   if (src) {
     a.mode = 3;
     a.src = src;
     a.n_src = n_src;
     a.pieces = pieces;
   }
-  a.max_crossings = tp->max_crossings;
-  a.kappa = kappa;
-  a.kappa_comp = kappa_comp;
-  a.status = ray_status;
-  a.hash = tp->crossing_hash;
-  a.count = tp->crossing_count;
-  a.log = tp->crossing_log;
-  a.log_stride = tp->log_stride;
   a.queue = p->queue;
   const int grid_waves = p->cu_count * waves_per_cu;
   // A long window can be marched in passes: each pass stops every ray on the
@@ -952,7 +971,6 @@ rr_status launch_trace(rr_plan p, rr_tensor t, const rr_trace_params* tp, const 
   // Only without debug outputs or a crossing limit, and with the Kahan state
   // kept in memory between passes.
   const bool debug = tp->crossing_hash || tp->crossing_count || tp->crossing_log;
-  a.pause_chi = -INFINITY;
   if (passes > 1 && (debug || tp->max_crossings > 0 ||
                      (t->precision == RR_PREC_FP32_KAHAN && !kappa_comp && !src)))
     passes = 1;
@@ -1082,6 +1100,59 @@ rr_status rr_graph_launch(rr_plan p, rr_stream s) {
   // the graph's tables are released only after this replay has finished
   for (auto& c : p->tables)
     if (c.in_graph) RR_HIP(hipEventRecord(c.used, (hipStream_t)s), "bundle table event");
+  return RR_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+rr_status rr_trace_rays_noalloc(rr_tensor t, const rr_trace_params* tp, const rr_bundle* bundles,
+                                int32_t n_bundles, void* kappa, float* kappa_comp,
+                                int32_t* ray_status, rr_stream s) {
+  rr_status st = validate_trace(t, tp, bundles, n_bundles);
+  if (st != RR_OK) return st;
+  if (!kappa) return fail(RR_ERR_INVALID_ARG, "kappa is NULL");
+  if (kappa_comp && t->precision != RR_PREC_FP32_KAHAN)
+    return fail(RR_ERR_INVALID_ARG, "kappa_comp is only used by FP32_KAHAN");
+  if (n_bundles > rr::kNoallocMaxBundles)
+    return fail(RR_ERR_CAPACITY,
+                "rr_trace_rays_noalloc takes at most %d bundles (its fixed device table); got %d",
+                rr::kNoallocMaxBundles, n_bundles);
+  const hipStream_t hs = (hipStream_t)s;
+  void* queue = nullptr;
+  rr::DevBundle* table = nullptr;
+  RR_HIP(rr::noalloc_scratch(&queue, &table), "scratch array address");
+  const int persistent = tp->persistent > 0 ? 1 : 0;
+  // the table goes to the scratch array in chunks built on the stack
+  int32_t order[rr::kNoallocMaxBundles];
+  launch_order(bundles, n_bundles, persistent, order);
+  constexpr int kChunk = 48;
+  rr::DevBundle chunk[kChunk];
+  int64_t tiles = 0;
+  for (int32_t k = 0; k < n_bundles; k += kChunk) {
+    const int m = std::min<int32_t>(kChunk, n_bundles - k);
+    for (int i = 0; i < m; ++i) tiles = table_entry(t, bundles[order[k + i]], tiles, &chunk[i]);
+    RR_HIP(rr::launch_put_bundles(table + k, chunk, m, hs), "bundle table launch");
+  }
+  if (tiles == 0) return RR_OK;
+  rr::TraceArgs a{};
+  march_args(t, tp, kappa, kappa_comp, ray_status, &a);
+  a.bundles = table;
+  a.n_bundles = n_bundles;
+  a.n_tiles = tiles;
+  a.queue = static_cast<unsigned long long*>(queue);
+  int dev = 0, cus = 0;
+  RR_HIP(hipGetDevice(&dev), "hipGetDevice");
+  RR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+  const int grid_waves = cus * 16;
+  if (persistent) RR_HIP(rr::launch_queue_reset(a.queue, hs), "queue reset");
+  if (t->kind == RR_GRID_UNIFORM) {
+    RR_HIP(rr::launch_march_uniform(t->precision, t->data, a, persistent, 256, grid_waves, hs),
+           "march launch");
+  } else {
+    RR_HIP(t->oct->march(a, persistent, grid_waves, hs), "octree march launch");
+  }
   return RR_OK;
 }
 

@@ -91,6 +91,13 @@ hipError_t launch_ray_bounds(const TraceArgs& a, int* out, hipStream_t s);
 hipError_t launch_march_uniform(int precision, const void* tv, const TraceArgs& a, int persistent,
                                 int block, int grid_waves, hipStream_t s);
 hipError_t launch_queue_reset(unsigned long long* q, hipStream_t s);
+// The allocation-free trace: bundles it takes at most, and the addresses (on
+// the current device) of the queue counter and the bundle table inside the
+// library's fixed device scratch array (resolved once per device).
+constexpr int kNoallocMaxBundles = 1024;
+hipError_t noalloc_scratch(void** queue, DevBundle** table);
+// dst[0..count) = host[0..count), by kernels whose arguments carry the entries
+hipError_t launch_put_bundles(DevBundle* dst, const DevBundle* host, int count, hipStream_t s);
 // p[0..n) = v (a kernel: safe inside a graph capture)
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 // kappa of every source from the moment state and the pieces (mode 3)
