@@ -583,6 +583,46 @@ def host_cpu():
     return model, max(len(sockets), 1), max(int(cores or 1), 1)
 
 
+def batched_profile(args, api, I, torch, dev):
+    """The 64 batched bundles alone, for profilers: one tensor build of the AMR
+    tree and --profile-reps persistent launches of all bundles in the shape the
+    tuner picks for them (16 wavefronts per CU, 16 passes)."""
+    case = I.config3()
+    tr = case.tree
+    grid = api.Grid(torch.as_tensor(case.phi.astype(np.float32), device=dev), case.box,
+                    n_base=tr.n, child_oct=torch.as_tensor(tr.child_oct, device=dev),
+                    max_level=tr.max_level)
+    tens = api.TidalTensor(grid, "fp32").build(grid)
+    plan = api.Plan()
+    bundles, offset = [], 0
+    for s in I.config4_specs():
+        bb = I.bundle_from_spec(s)
+        bundles.append(api.RayBundle(torch.as_tensor(bb.dirs, device=dev), bb.nx, bb.ny,
+                                     bb.chi_s, bb.chi_hi, bb.chi_lo, offset))
+        offset += bb.nx * bb.ny
+    plan.set_shape(bundles, persistent=1, waves_per_cu=16, passes=args.amr_passes)
+    kap = torch.zeros(offset, dtype=torch.float32, device=dev)
+    comp = torch.zeros(offset, dtype=torch.float32, device=dev)
+    ms = []
+    for _ in range(args.profile_reps):
+        kap.zero_()
+        comp.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.trace(plan, tens, bundles, case.observer, kappa=kap, kappa_comp=comp, persistent=-1)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+        log(f"batched bundles, {args.amr_passes} passes: {ms[-1]:.1f} ms")
+    return {"batched_profile": {"passes": args.amr_passes, "ms": ms, "rays": offset}}
+
+
+def adjoint_profile(args, api, I, torch, dev):
+    """The adjoint configuration alone, for profilers: --profile-reps forward and
+    backward steps (tensor build, march, scatter and transpose)."""
+    args.steps, args.warmup = args.profile_reps, 0
+    return {"adjoint_profile": adjoint_leg(args, api, I, torch, dev)}
+
+
 def cpu_baseline(ctx, results, target_s):
     """FP64 oracle on the host over the whole light cone (every segment with
     its own vertex tensor) for a deterministic ray sample, on all the cores
@@ -610,12 +650,14 @@ def cpu_baseline(ctx, results, target_s):
         t0 = time.perf_counter()
         tv = O.vertex_tensor(phi)
         t_tensor += time.perf_counter() - t0
-        t0 = time.perf_counter()
-        r = O.trace_uniform(n, box, obs, dirs[sel], chi_s, hi, lo, tv=tv, threads=cores)
-        t_trace += time.perf_counter() - t0
+        # one thread first: the oracle keeps the last thread count, and the
+        # all-thread call below restores it for the next segment's tensor
         t0 = time.perf_counter()
         r1 = O.trace_uniform(n, box, obs, dirs[one], chi_s, hi, lo, tv=tv, threads=1)
         t_one += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = O.trace_uniform(n, box, obs, dirs[sel], chi_s, hi, lo, tv=tv, threads=cores)
+        t_trace += time.perf_counter() - t0
         cross_one += int(r1.ncross.sum())
         kap += r.kappa
         cross += int(r.ncross.sum())
@@ -677,7 +719,13 @@ def main():
     ap.add_argument("--profile-amr", action="store_true",
                     help="AMR map only (for profilers): tensor build and two marches")
     ap.add_argument("--amr-passes", type=int, default=16,
-                    help="passes of the --profile-amr march")
+                    help="passes of the --profile-amr and --profile-batched marches")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="the 64 batched bundles only (for profilers)")
+    ap.add_argument("--profile-adjoint", action="store_true",
+                    help="the adjoint configuration only (for profilers)")
+    ap.add_argument("--profile-reps", type=int, default=2,
+                    help="launches of the --profile-batched / --profile-adjoint modes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the light cone, copy this many MiB device-to-device (a plain "
                          "copy kernel that calibrates the profiler's byte counters)")
@@ -697,6 +745,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.profile_amr:
         print(json.dumps(amr_profile(args, api, I, torch, dev)), flush=True)
+        return
+    if args.profile_batched:
+        print(json.dumps(batched_profile(args, api, I, torch, dev)), flush=True)
+        return
+    if args.profile_adjoint:
+        print(json.dumps(adjoint_profile(args, api, I, torch, dev)), flush=True)
         return
     results, ctx = lightcone_leg(args, api, I, torch, dev)
     r32 = results["fp32"]

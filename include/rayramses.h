@@ -361,7 +361,7 @@ rr_status rr_rays_vertex_box(rr_plan p, rr_tensor t, const rr_trace_params* tp,
 /* Tune the launch shape for this bundle set: times one-wavefront-per-tile
  * launches (64- and 256-thread workgroups) and persistent workgroups fed by
  * the device queue (8, 16 or 32 wavefronts per compute unit), each as one
- * pass over the chi window or split into 4 or 16 passes, on scratch outputs,
+ * pass over the chi window or split into 4 to 64 passes, on scratch outputs,
  * and remembers the fastest for the bundle set; later rr_trace_rays /
  * rr_trace_rays_sources calls with tp->persistent = -1 and the same bundles
  * use it.  A split march cuts the bundles' chi range into equal steps: a pass
@@ -412,6 +412,10 @@ rr_status rr_trace_rays_adjoint(rr_plan p, rr_tensor t, const rr_field_desc* f,
  * table and the persistent queue counter live in a fixed device array of the
  * library (72.5 KiB per GPU, held until the process ends; its address is
  * resolved once per device), written by kernels on s before the march.
+ * Tiles go to the wavefronts in the same order as rr_trace_rays (bundles as
+ * given, or longest chi window first for persistent launches; Z order of
+ * the 8 x 8 tiles within a bundle; persistent launches use one counter per
+ * chiplet).
  *  - n_bundles <= 1024, else RR_ERR_CAPACITY (nothing enqueued).
  *  - tp->persistent: 1 = persistent workgroups (16 wavefronts per compute
  *    unit) fed by the queue counter; 0 or -1 = one wavefront per 8x8 tile

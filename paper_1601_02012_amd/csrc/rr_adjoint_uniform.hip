@@ -34,6 +34,7 @@ __device__ __forceinline__ void corner_weights(const float* uA, const float* uB,
                                                float chiB, float DB, float inv_chis, float* om) {
   const float cs[3] = {(float)GL3::c0, (float)GL3::c1, (float)GL3::c2};
   const float ws[3] = {(float)GL3::w0, (float)GL3::w1, (float)GL3::w2};
+  const float s = L * inv_chis;
 #pragma unroll
   for (int v = 0; v < 8; ++v) om[v] = 0.0f;
 #pragma unroll
@@ -43,7 +44,7 @@ __device__ __forceinline__ void corner_weights(const float* uA, const float* uB,
     const float uy = fmaf(uA[1] - uB[1], c, uB[1]);
     const float uz = fmaf(uA[2] - uB[2], c, uB[2]);
     const float chik = fmaf(L, c, chiB);
-    const float W = ws[k] * chik * fmaf(-L, c, DB);
+    const float W = (ws[k] * s) * chik * fmaf(-L, c, DB);
     const float z1 = W * uz, z0 = W - z1;
     const float y1z0 = uy * z0, y0z0 = z0 - y1z0, y1z1 = uy * z1, y0z1 = z1 - y1z1;
     om[0] = fmaf(1.0f - ux, y0z0, om[0]);
@@ -55,9 +56,6 @@ __device__ __forceinline__ void corner_weights(const float* uA, const float* uB,
     om[6] = fmaf(1.0f - ux, y1z1, om[6]);
     om[7] = fmaf(ux, y1z1, om[7]);
   }
-  const float s = L * inv_chis;
-#pragma unroll
-  for (int v = 0; v < 8; ++v) om[v] *= s;
 }
 
 // x of another lane of the same row of 16, picked by a DPP lane pattern.
@@ -88,26 +86,21 @@ __device__ __forceinline__ void fold(float* x, bool hi) {
 // groups of lanes a few steps apart; their sums meet in the cache, and a
 // vertex goes to global memory (six FP32 atomics) when its slot is taken by
 // another vertex or the tile ends.
+// Vertex ids are 32 bit when the grid has fewer than 2^32 - 1 vertices.
+template <typename Id>
 struct CacheSlot {
-  uint64_t tag;   // vertex id, or kEmpty
+  Id tag;         // vertex id, or empty (all bits set)
   float v[6];
 };
 constexpr int kSlots = 256;   // x & 7, y & 7, z & 3
-constexpr uint64_t kEmpty = ~0ull;
 
-__device__ __forceinline__ void flush_slot(float* __restrict__ lam, const CacheSlot& e) {
-  if (e.tag != kEmpty) {
-    float* dst = lam + e.tag * 6;
+template <typename Id>
+__device__ __forceinline__ void flush_slot(float* __restrict__ lam, const CacheSlot<Id>& e) {
+  if (e.tag != (Id)~(Id)0) {
+    float* dst = lam + (uint64_t)e.tag * 6;
 #pragma unroll
     for (int c = 0; c < 6; ++c) atomicAdd(dst + c, e.v[c]);
   }
-}
-
-// Corner v = ix + 2 iy + 4 iz of a cell that is the j-th corner (j = 0..3,
-// ordered by the two coordinates along the face) of face F = 2 axis + side.
-__device__ __forceinline__ int face_corner(int F, int j) {
-  const int k = F >> 1, s = F & 1;
-  return k == 0 ? (s | (j << 1)) : (k == 1 ? ((j & 1) | (s << 1) | ((j >> 1) << 2)) : (j | (s << 2)));
 }
 
 // Retire face F of cell (W0, W1, W2) for the lanes with `mine` set: corner j
@@ -117,8 +110,11 @@ __device__ __forceinline__ int face_corner(int F, int j) {
 // values summed over 8 lanes, which the row (bit 3) and the other rows
 // (register swaps of 16- and 32-lane groups) then complete; lanes 0..7 hold
 // all 24 sums, corner 2 b0 + b1 and components 3 b2 .. 3 b2 + 2, and update
-// the cache side by side.  Called with all 64 lanes active; F and W are wavefront-uniform.
-__device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* cache,
+// the cache side by side.  Called with all 64 lanes active; F and W are
+// wavefront-uniform, so the four corners' vertex ids and cache slots are
+// formed once per wavefront (scalar registers) and each lane picks its own.
+template <typename Id>
+__device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot<Id>* cache,
                                             const float* acc, const float* P, bool mine, int F,
                                             int W0, int W1, int W2, int n, int lane) {
   float a[4];
@@ -132,7 +128,8 @@ __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* 
   }
   // the first halving step is taken on the products as they are formed: a
   // lane with bit 0 set keeps corners 2 and 3 and sends 0 and 1, a lane
-  // with it clear the reverse
+  // with it clear the reverse (the sent products are added by the DPP move
+  // itself: keep * P is rounded on its own first)
   const bool h0 = (lane & 1) != 0;
   float x[12];
 #pragma unroll
@@ -140,7 +137,8 @@ __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* 
     const float al = mine ? a[j] : 0.0f, ah = mine ? a[j + 2] : 0.0f;
     const float keep = h0 ? ah : al, send = h0 ? al : ah;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) x[6 * j + c] = fmaf(keep, P[c], dpp_lane<0xb1>(send * P[c]));
+    for (int c = 0; c < 6; ++c)
+      x[6 * j + c] = __fmul_rn(keep, P[c]) + dpp_lane<0xb1>(__fmul_rn(send, P[c]));
   }                                      // quad_perm [1,0,3,2]: lane ^ 1
   fold<0x4e, 6>(x, (lane & 2) != 0);     // quad_perm [2,3,0,1]: lane ^ 2
   fold<0x124, 3>(x, (lane & 4) != 0);    // row_ror:4: lane - 4 within the row
@@ -156,29 +154,34 @@ __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* 
                                                       false, false);
     x[i] = __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
   }
+  // the face's corners j = i_a + 2 i_b (a < b the two axes other than the
+  // face's axis k = F / 2, which sits at layer F % 2): their lattice
+  // coordinates take one of two values per axis, formed once per wavefront
+  const int k = F >> 1, sd = F & 1;
+  const int X1 = W0 + 1 == n ? 0 : W0 + 1, Y1 = W1 + 1 == n ? 0 : W1 + 1;
+  const int Z1 = W2 + 1 == n ? 0 : W2 + 1;
   if (lane < 8) {
-    const int j = 2 * (lane & 1) + ((lane >> 1) & 1);
+    const int ia = (lane >> 1) & 1, ib = lane & 1;   // lane bits 1, 0: j = 2 b0 + b1
+    const int bx = k == 0 ? sd : ia;
+    const int by = k == 1 ? sd : (k == 0 ? ia : ib);
+    const int bz = k == 2 ? sd : ib;
+    const int cx = bx ? X1 : W0, cy = by ? Y1 : W1, cz = bz ? Z1 : W2;
+    const Id my_vid = ((Id)cz * (Id)n + (Id)cy) * (Id)n + (Id)cx;
+    const int my_slot = ((W0 + bx) & 7) | (((W1 + by) & 7) << 3) | (((W2 + bz) & 3) << 6);
     const int cb = (lane & 4) ? 3 : 0;
-    const int v = face_corner(F, j);
-    int cx = W0 + (v & 1), cy = W1 + ((v >> 1) & 1), cz = W2 + (v >> 2);
-    const int slot = (cx & 7) | ((cy & 7) << 3) | ((cz & 3) << 6);
-    cx = cx == n ? 0 : cx;
-    cy = cy == n ? 0 : cy;
-    cz = cz == n ? 0 : cz;
-    const uint64_t vid = ((uint64_t)cz * (uint64_t)n + (uint64_t)cy) * (uint64_t)n + (uint64_t)cx;
-    CacheSlot& e = cache[slot];
-    const uint64_t tag = e.tag;
-    if (tag == vid) {
+    CacheSlot<Id>& e = cache[my_slot];
+    const Id tag = e.tag;
+    if (tag == my_vid) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) e.v[cb + i] += x[i];
     } else {
-      if (tag != kEmpty) {
+      if (tag != (Id)~(Id)0) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) atomicAdd(lam + tag * 6 + cb + i, e.v[cb + i]);
+        for (int i = 0; i < 3; ++i) atomicAdd(lam + (uint64_t)tag * 6 + cb + i, e.v[cb + i]);
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) e.v[cb + i] = x[i];
-      if (cb == 0) e.tag = vid;
+      if (cb == 0) e.tag = my_vid;
     }
   }
 }
@@ -186,10 +189,11 @@ __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot* 
 // One 8 x 8 tile of rays, all 64 lanes kept active to the end (lanes without
 // a ray, or whose ray has ended, take part in the wavefront reductions with
 // nothing to add).
+template <typename Id>
 __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int iy, int lane,
                              const float* __restrict__ wts, float* __restrict__ lam,
-                             CacheSlot* cache) {
-  for (int e = lane; e < kSlots; e += 64) cache[e].tag = kEmpty;
+                             CacheSlot<Id>* cache) {
+  for (int e = lane; e < kSlots; e += 64) cache[e].tag = (Id)~(Id)0;
   bool alive = ix < B.nx && iy < B.ny;
   const int64_t ray = alive ? (int64_t)iy * B.nx + ix : 0;
   const int64_t out = B.ray_offset + ray;
@@ -300,7 +304,7 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
       const int W1 = __builtin_amdgcn_readlane(w[1], leader);
       const int W2 = __builtin_amdgcn_readlane(w[2], leader);
       const bool mine = f0 == F && w[0] == W0 && w[1] == W1 && w[2] == W2;
-      retire_face(lam, cache, acc, P, mine, F, W0, W1, W2, n, lane);
+      retire_face<Id>(lam, cache, acc, P, mine, F, W0, W1, W2, n, lane);
       if (mine) {
         f0 = f1;
         f1 = -1;
@@ -355,9 +359,10 @@ __device__ void scatter_tile(const TraceArgs& a, const DevBundle& B, int ix, int
   for (int e = lane; e < kSlots; e += 64) flush_slot(lam, cache[e]);
 }
 
+template <typename Id>
 __global__ __launch_bounds__(256) void scatter_kernel(TraceArgs a, const float* __restrict__ wts,
                                                       float* __restrict__ lam) {
-  __shared__ CacheSlot cache[4][kSlots];
+  __shared__ CacheSlot<Id> cache[4][kSlots];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t nblk = gridDim.x, blk = blockIdx.x;
@@ -369,8 +374,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(TraceArgs a, const float* 
   const DevBundle& B = a.bundles[b];
   const int64_t local = tile - B.tile_begin;
   const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
-  scatter_tile(a, B, tx * 8 + (lane & 7), ty * 8 + (lane >> 3), lane, wts, lam,
-               cache[__builtin_amdgcn_readfirstlane(wave)]);
+  scatter_tile<Id>(a, B, tx * 8 + (lane & 7), ty * 8 + (lane >> 3), lane, wts, lam,
+                   cache[__builtin_amdgcn_readfirstlane(wave)]);
 }
 
 // Transpose stencil, built like the forward tensor: a workgroup owns a
@@ -505,7 +510,12 @@ hipError_t launch_adjoint_uniform(const TraceArgs& a, const float* dl_dkappa, fl
   if (a.n_tiles > 0) {
     int64_t blocks = (a.n_tiles + 3) / 4;
     blocks = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, dl_dkappa, lam);
+    if (nv < (int64_t)0xffffffffll)
+      hipLaunchKernelGGL(scatter_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, a,
+                         dl_dkappa, lam);
+    else
+      hipLaunchKernelGGL(scatter_kernel<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, a,
+                         dl_dkappa, lam);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

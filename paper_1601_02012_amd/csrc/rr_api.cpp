@@ -106,7 +106,7 @@ struct TunedShape {
 }  // namespace
 
 struct rr_plan_s {
-  unsigned long long* queue = nullptr;   // work queue counter; bytes 64.. hold ray bounds
+  unsigned long long* queue = nullptr;   // eight work counters (one per XCD); bytes 64.. hold ray bounds
   std::vector<CachedTable> tables;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -815,9 +815,10 @@ rr_status rr_plan_autotune(rr_plan p, rr_tensor t, const rr_trace_params* tp,
   q.crossing_log = nullptr;
   q.log_stride = 0;
   struct Cand { int persistent, block, waves, passes; };
-  const Cand cands[] = {{0, 256, 0, 1},  {0, 64, 0, 1},   {1, 256, 8, 1},  {1, 256, 16, 1},
-                        {1, 256, 32, 1}, {0, 256, 0, 4},  {0, 256, 0, 16}, {0, 64, 0, 16},
-                        {1, 256, 16, 16}};
+  const Cand cands[] = {{0, 256, 0, 1},   {0, 64, 0, 1},    {1, 256, 8, 1},  {1, 256, 16, 1},
+                        {1, 256, 32, 1},  {0, 256, 0, 4},   {0, 256, 0, 16}, {0, 64, 0, 16},
+                        {1, 256, 16, 16}, {0, 256, 0, 32},  {1, 256, 16, 32}, {0, 256, 0, 64},
+                        {1, 256, 16, 64}};
   hipEvent_t e0, e1;
   RR_HIP(hipEventCreate(&e0), "event");
   RR_HIP(hipEventCreate(&e1), "event");

@@ -461,8 +461,8 @@ __device__ __forceinline__ void run_tile(const R* __restrict__ tv, const TraceAr
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
   const DevBundle& B = a.bundles[b];
-  const int64_t local = tile - B.tile_begin;
-  const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
+  int tx, ty;
+  zorder_tile(tile - B.tile_begin, B.tiles_x, B.tiles_y, tx, ty);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
   if (ix < B.nx && iy < B.ny) trace_one<R, kDebug, Off, kMode, kPass>(tv, a, B, (int64_t)iy * B.nx + ix);
 }
@@ -489,25 +489,25 @@ void march_uniform_kernel(const R* __restrict__ tv,
   run_tile<R, kDebug, Off, kMode, kPass>(tv, a, tile, lane);
 }
 
-// Persistent workgroups: every wavefront pulls tiles from a device counter
-// until the queue is drained (every wave reaches the exit test).
+// Persistent workgroups: every wavefront pulls tiles from its chiplet's
+// counter, then from the others', until all are drained (every wave reaches
+// the exit test).  The tile is the same for the 64 lanes: it (and the
+// bundle) stays scalar.
 template <typename R, bool kDebug, typename Off, int kMode, bool kPass>
 __global__ __launch_bounds__(256) void march_uniform_persistent(const R* __restrict__ tv,
                                                                 TraceArgs a) {
   const int lane = threadIdx.x & 63;
+  int q = blockIdx.x % kQueues, tried = 0;
   for (;;) {
-    unsigned long long t = 0;
-    if (lane == 0) t = atomicAdd(a.queue, 1ull);
-    t = __shfl(t, 0, 64);
-    // the tile is the same for the 64 lanes: keep it (and the bundle) scalar
-    const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
-                                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
-    if (tile >= a.n_tiles) break;
+    const int64_t tile = next_tile(a.queue, a.n_tiles, q, tried, lane);
+    if (tile < 0) break;
     run_tile<R, kDebug, Off, kMode, kPass>(tv, a, tile, lane);
   }
 }
 
-__global__ void queue_reset_kernel(unsigned long long* q) { *q = 0ull; }
+__global__ void queue_reset_kernel(unsigned long long* q) {
+  if (threadIdx.x < kQueues) q[threadIdx.x] = 0ull;
+}
 
 __global__ __launch_bounds__(256) void fill_kernel(double* __restrict__ p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -622,7 +622,7 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
 }
 
 hipError_t launch_queue_reset(unsigned long long* q, hipStream_t s) {
-  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, s, q);
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, s, q);
   return hipGetLastError();
 }
 

@@ -758,8 +758,8 @@ __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const Trace
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
   const DevBundle& B = a.bundles[b];
-  const int64_t local = tile - B.tile_begin;
-  const int tx = (int)(local % B.tiles_x), ty = (int)(local / B.tiles_x);
+  int tx, ty;
+  zorder_tile(tile - B.tile_begin, B.tiles_x, B.tiles_y, tx, ty);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
   if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kMode, Off>(T, cv, a, B, (int64_t)iy * B.nx + ix);
 }
@@ -780,13 +780,10 @@ __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __re
 template <typename R, bool kDebug, int kMode, typename Off>
 __global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* __restrict__ cv, TraceArgs a) {
   const int lane = threadIdx.x & 63;
+  int q = blockIdx.x % kQueues, tried = 0;
   for (;;) {
-    unsigned long long t = 0;
-    if (lane == 0) t = atomicAdd(a.queue, 1ull);
-    t = __shfl(t, 0, 64);
-    const int64_t tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32)) << 32) |
-                                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
-    if (tile >= a.n_tiles) break;
+    const int64_t tile = next_tile(a.queue, a.n_tiles, q, tried, lane);
+    if (tile < 0) break;
     oct_tile<R, kDebug, kMode, Off>(T, cv, a, tile, lane);
   }
 }

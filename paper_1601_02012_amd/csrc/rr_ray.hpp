@@ -258,6 +258,64 @@ __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
   sum = t;
 }
 
+// Position of the k-th 8 x 8 tile of a bundle's tiles_x x tiles_y tile grid
+// in Z order (quadrants (0,0), (1,0), (0,1), (1,1) at every level of the
+// enclosing power-of-two square, positions outside the grid skipped): tiles
+// that are close in launch order are close on the sky, so the wavefronts
+// working at the same time, and the ones that share a chiplet, gather from
+// the same part of the field.  k is wavefront-uniform (scalar work).
+__device__ __forceinline__ void zorder_tile(int64_t k, int W, int H, int& x, int& y) {
+  int s = 1;
+  while (s < W || s < H) s <<= 1;
+  int x0 = 0, y0 = 0;
+  while (s > 1) {
+    const int h = s >> 1;
+    const int64_t w0 = min(max(W - x0, 0), h), w1 = min(max(W - x0 - h, 0), h);
+    const int64_t h0 = min(max(H - y0, 0), h), h1 = min(max(H - y0 - h, 0), h);
+    s = h;
+    if (k < w0 * h0) continue;
+    k -= w0 * h0;
+    if (k < w1 * h0) {
+      x0 += h;
+      continue;
+    }
+    k -= w1 * h0;
+    if (k < w0 * h1) {
+      y0 += h;
+      continue;
+    }
+    k -= w0 * h1;
+    x0 += h;
+    y0 += h;
+  }
+  x = x0;
+  y = y0;
+}
+
+// Persistent launches: one work counter per chiplet (XCD).  Workgroups are
+// dealt to the eight XCDs round-robin, so workgroup b runs on XCD b % 8; the
+// tiles are split into eight contiguous ranges of the launch order, each
+// chiplet drains its own range first (its L2 sees one compact part of the
+// sky) and then helps with the others.  Returns the next tile, or -1 once
+// every range is empty (every wavefront reaches that exit).
+constexpr int kQueues = 8;
+__device__ __forceinline__ int64_t next_tile(unsigned long long* queue, int64_t n_tiles, int& q,
+                                             int& tried, int lane) {
+  while (tried < kQueues) {
+    const int64_t lo = n_tiles * q / kQueues, hi = n_tiles * (q + 1) / kQueues;
+    unsigned long long t = 0;
+    if (lane == 0) t = atomicAdd(queue + q, 1ull);
+    t = __shfl(t, 0, 64);
+    const int64_t k = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> 32))
+                                 << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
+    if (k < hi - lo) return lo + k;
+    q = q + 1 == kQueues ? 0 : q + 1;
+    ++tried;
+  }
+  return -1;
+}
+
 // Work assignment: global tile index -> (bundle, tile within it).
 __device__ __forceinline__ int find_bundle(const DevBundle* b, int nb, int64_t tile) {
   int lo = 0, hi = nb - 1;
