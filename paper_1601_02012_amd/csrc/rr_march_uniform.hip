@@ -417,6 +417,14 @@ __device__ void trace_one(const R* __restrict__ tv, const TraceArgs& a, const De
         const R F1 = project<R, Off>(tv, w1, P);
         const R F2 = project<R, Off>(tv, w0 + db, P);
         const R F3 = project<R, Off>(tv, w1 + db, P);
+        if (__ballot(!k0 && !k1) == __ballot(1)) {
+          // every marching lane crossed a z face (lines of sight near the z
+          // axis): the old exit face becomes the entry face, no selects
+          q[0] = q[4]; q[1] = q[5]; q[2] = q[6]; q[3] = q[7];
+          q[4] = F0; q[5] = F1; q[6] = F2; q[7] = F3;
+          chiA = chiB;
+          continue;
+        }
         const R n0 = k0 ? q[1] : (k1 ? q[2] : q[4]);
         const R n1 = k0 ? F0 : (k1 ? q[3] : q[5]);
         const R n2 = k0 ? q[3] : (k1 ? F0 : q[6]);

@@ -654,7 +654,13 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
         const R F1 = leaf_corner<R, Off>(cv, nc, (sk | sa) ^ flip, P);
         const R F2 = leaf_corner<R, Off>(cv, nc, (sk | sb) ^ flip, P);
         const R F3 = leaf_corner<R, Off>(cv, nc, (sk | sa | sb) ^ flip, P);
-        if (kc < 0) {
+        if (__ballot(kc < 0 && !k0 && !k1) == __ballot(1)) {
+          // every marching lane crossed a z face into a leaf of its level
+          // (lines of sight near the z axis): no selects
+          q[0] = q[4]; q[1] = q[5]; q[2] = q[6]; q[3] = q[7];
+          q[4] = F0; q[5] = F1; q[6] = F2; q[7] = F3;
+          kept = true;
+        } else if (kc < 0) {
           const R n0 = k0 ? q[1] : (k1 ? q[2] : q[4]);
           const R n1 = k0 ? F0 : (k1 ? q[3] : q[5]);
           const R n2 = k0 ? q[3] : (k1 ? F0 : q[6]);
