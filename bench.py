@@ -44,6 +44,13 @@ PEAK_FP32_TFLOPS = 157.3
 # and tie tests (6 comparisons), exit coordinates (3), the piece length and
 # chi_s - chi_B (2) and the next plane's parameter (2) in FP64
 FLOPS_PER_CROSSING = {"fp32": 156, "fp64": 13}
+# arithmetic of one crossing of the adjoint scatter, counted the same way: per
+# Gauss node the node's chi and kernel weight (6), its local coordinates (6),
+# the eight trilinear corner weights scaled by the node weight (3 + 2 + 4 + 8)
+# and their accumulation (8), after the piece's three coordinate differences
+# (3); when a face retires, its four corners' weights times the six projection
+# factors and their sums (24 + 24); the walk's 13 FP64 operations as above
+ADJ_FLOPS_PER_CROSSING = {"fp32": 3 * (6 + 6 + 17 + 8) + 3 + 48, "fp64": 13}
 BYTES_PER_VERTEX = {"fp32": 4 + 24, "fp64": 4 + 48}  # potential in, 6 components out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_traffic.md")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_counters.md")
@@ -524,13 +531,21 @@ def adjoint_leg(args, api, I, torch, dev):
     t.close()
     del grad, kap, comp, dphi
     torch.cuda.empty_cache()
+    flops_eq = ADJ_FLOPS_PER_CROSSING["fp32"] + 2 * ADJ_FLOPS_PER_CROSSING["fp64"]
+    achieved = flops_eq * cross / (bwd_ms * 1e-3) / 1e12
     return {"workload": "adjoint: L = sum(w kappa), w ~ N(0,1), 1024x1024 rays over 5x5 deg "
                         "to chi_s = 256 Mpc/h through a 256^3 FP32 Gaussian potential (box "
                         "256 Mpc/h); backward through the march, the vertex mean and the "
                         "stencil to dL/dPhi",
             "crossings": cross, "ms_per_step": ms, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
             "backward_crossings_per_s": cross / (bwd_ms * 1e-3),
-            "dot_product_identity_rel_diff": abs(lhs - rhs) / max(abs(lhs), abs(rhs), 1e-300)}
+            "dot_product_identity_rel_diff": abs(lhs - rhs) / max(abs(lhs), abs(rhs), 1e-300),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                         "flops_per_crossing": {**ADJ_FLOPS_PER_CROSSING,
+                                                "fp32_equivalent": flops_eq},
+                         "kernel": "the backward call (scatter_kernel, then transpose_kernel), "
+                                   "timed with HIP events on its stream"}}
 
 
 def amr_profile(args, api, I, torch, dev):
