@@ -783,8 +783,14 @@ __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __re
   oct_tile<R, kDebug, kMode, Off>(T, cv, a, tile, lane);
 }
 
+// The FP32 tidal march (no debug outputs, 32-bit offsets) fits 128 VGPRs
+// without spilling: four waves per SIMD keep a 16-wave-per-CU persistent grid
+// resident at once (at 132 VGPRs only three were; the 64 batched bundles
+// 2.34 -> 2.02 s).  The other instantiations spill under that cap.
 template <typename R, bool kDebug, int kMode, typename Off>
-__global__ __launch_bounds__(256) void march_octree_persistent(Tree T, const R* __restrict__ cv, TraceArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    sizeof(R) == 4 && kMode == 0 && !kDebug && sizeof(Off) == 4 ? 4 : 1)))
+void march_octree_persistent(Tree T, const R* __restrict__ cv, TraceArgs a) {
   const int lane = threadIdx.x & 63;
   int q = blockIdx.x % kQueues, tried = 0;
   for (;;) {

@@ -79,6 +79,13 @@ __global__ __launch_bounds__(64 * TY) void vertex_tensor_uniform_kernel(const In
   constexpr int NT = TX * TY;                 // threads
   constexpr int PX = TX + 3, PY = TY + 3;     // staged plane: halo 2 below, 1 above
   __shared__ Acc plane[2][PY * PX];
+  // FP64 records of whole-grid builds leave through LDS: each wavefront (one
+  // row of 64 vertices) writes its 3 KiB row with contiguous 16-byte stores
+  // instead of three 16-byte stores per lane at a 48-byte stride (2.2 ->
+  // 1.8 ms for 512^3).  FP32 rows keep per-lane stores: the staging buffer
+  // would cost the second workgroup per CU (0.78 -> 0.99 ms).
+  constexpr bool kRowStore = kNT && sizeof(Acc) == 8;
+  __shared__ __align__(16) Acc rowbuf[kRowStore ? TY : 1][kRowStore ? TX * RW : 1];
 
   const int b = blockIdx.x;
   const int bx = b % V.ntx;
@@ -92,6 +99,10 @@ __global__ __launch_bounds__(64 * TY) void vertex_tensor_uniform_kernel(const In
   i = i >= n ? i - n : i;
   j = j >= n ? j - n : j;
   const int64_t nn = (int64_t)n * n;
+  // the wavefront's row is whole, does not wrap and starts 16-byte aligned
+  int i_row = V.ox + li0;
+  i_row = i_row >= n ? i_row - n : i_row;
+  const bool row_ok = kRowStore && li0 + TX <= V.sx && lj0 + ty < V.sy && i_row + TX <= n;
 
   // per-plane partial stencils, history over planes (index 0 = oldest)
   Acc XX[2], YY[2], XY[2];     // planes k-1, k
@@ -206,7 +217,26 @@ __global__ __launch_bounds__(64 * TY) void vertex_tensor_uniform_kernel(const In
 #pragma unroll
         for (int c = 0; c < 6; ++c) rec[c] = nan;
       }
-      store_vertex<kNT>(tv + ((int64_t)k * nn + (int64_t)j * n + i) * RW, rec);
+      if (row_ok) {
+        // lanes write their records side by side in LDS, then read back
+        // 16-byte chunks of the row in order (LDS operations of one
+        // wavefront complete in order; the empty asm statements keep the
+        // compiler from moving the accesses across each other)
+        Acc* rb = rowbuf[kRowStore ? ty : 0];
+#pragma unroll
+        for (int c = 0; c < RW; ++c) rb[tx * RW + c] = rec[c];
+        __asm__ volatile("" ::: "memory");
+        typedef Acc chunk_t __attribute__((ext_vector_type(16 / sizeof(Acc))));
+        constexpr int kE = 16 / sizeof(Acc), kChunks = TX * RW / kE;
+        Acc* dst = tv + ((int64_t)k * nn + (int64_t)j * n + i_row) * RW;
+#pragma unroll
+        for (int m = tx; m < kChunks; m += TX)
+          __builtin_nontemporal_store(*reinterpret_cast<const chunk_t*>(rb + m * kE),
+                                      reinterpret_cast<chunk_t*>(dst + m * kE));
+        __asm__ volatile("" ::: "memory");
+      } else {
+        store_vertex<kNT>(tv + ((int64_t)k * nn + (int64_t)j * n + i) * RW, rec);
+      }
     }
     // XX/YY/XY hold planes (p-2, p-1) during step p; push plane p
     XX[0] = XX[1]; YY[0] = YY[1]; XY[0] = XY[1];
