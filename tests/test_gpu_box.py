@@ -124,23 +124,28 @@ def test_vertex_box_bounds_and_open_grid_clipping(api, plan):
     assert e.value.status == -6
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("lo", [(0, 0, 0), (64, 2, 5), (-3, 7, 9)])
-def test_large_box_and_whole_grid_streaming_builds(api, oracle, lo):
-    """n = 128 FP32: the whole-grid build (the streaming configuration, 64x8x64
-    columns) matches the oracle, and boxes above 1/8 of the grid (the same
-    configuration) -- with even, odd and wrapping origins -- equal it on their
-    vertices and leave the others alone."""
+def test_large_box_and_whole_grid_streaming_builds(api, oracle, lo, prec):
+    """n = 128: the whole-grid build (the streaming configuration, 64x16x16
+    columns; FP64 rows of records leave through LDS as contiguous 16-byte
+    stores, rows that wrap or stop short per lane) matches the oracle, and
+    boxes above 1/8 of the grid (the same configuration) -- with even, odd and
+    wrapping origins -- equal it on their vertices and leave the others
+    alone."""
     n, box = 128, 128.0
+    dt = np.float64 if prec == "fp64" else np.float32
     rng = np.random.default_rng(13)
-    phi = rng.standard_normal((n, n, n)).astype(np.float32)
+    phi = rng.standard_normal((n, n, n)).astype(dt)
     g = gpu_grid(api, phi, box)
-    whole = api.TidalTensor(g, "fp32").build().to_torch().cpu().numpy().reshape(n, n, n, 6)
+    whole = api.TidalTensor(g, prec).build().to_torch().cpu().numpy().reshape(n, n, n, 6)
     ref = oracle.vertex_tensor(phi.astype(np.float64)).reshape(n, n, n, 6)
-    np.testing.assert_allclose(whole, ref, rtol=0, atol=2e-6 * np.abs(ref).max())
+    tol = 1e-13 if prec == "fp64" else 2e-6
+    np.testing.assert_allclose(whole, ref, rtol=0, atol=tol * np.abs(ref).max())
     size = (128, 100, 40)
     assert 8 * np.prod(size) > n ** 3
-    poison = gpu_grid(api, (1e3 * rng.standard_normal((n, n, n))).astype(np.float32), box)
-    t = api.TidalTensor(poison, "fp32").build()
+    poison = gpu_grid(api, (1e3 * rng.standard_normal((n, n, n))).astype(dt), box)
+    t = api.TidalTensor(poison, prec).build()
     before = t.to_torch().cpu().numpy().reshape(n, n, n, 6)
     t.build_box(lo, size, grid=g)
     got = t.to_torch().cpu().numpy().reshape(n, n, n, 6)
