@@ -57,31 +57,40 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_counters
 MARCH_SOURCES = ["paper_1601_02012_amd/csrc/rr_march_uniform.hip",
                  "paper_1601_02012_amd/csrc/rr_ray.hpp",
                  "paper_1601_02012_amd/csrc/rr_internal.hpp"]
+ADJOINT_FILE = os.path.join(ROOT, "profiles", "adjoint_scatter_counters.md")
+ADJOINT_SOURCES = ["paper_1601_02012_amd/csrc/rr_adjoint_uniform.hip",
+                   "paper_1601_02012_amd/csrc/rr_ray.hpp",
+                   "paper_1601_02012_amd/csrc/rr_internal.hpp"]
 
 
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def march_source_hash():
+def source_hash(files=MARCH_SOURCES):
     h = hashlib.sha256()
-    for f in MARCH_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def profile_figures():
-    """Figures from the committed rocprofv3 summaries (HBM bytes per march launch, L2 hit
-    fraction, VALU busy fraction, VALU instructions per crossing), each kept only if the
-    summary was taken on the current march source."""
-    src = march_source_hash()
+def march_source_hash():
+    return source_hash(MARCH_SOURCES)
+
+
+def profile_figures(paths=(TRAFFIC_FILE, COUNTERS_FILE), files=MARCH_SOURCES,
+                    tag="march_source_sha256_16"):
+    """Figures from the committed rocprofv3 summaries (for the march: HBM bytes per
+    launch, L2 hit fraction, VALU busy fraction, VALU instructions per crossing), each
+    kept only if the summary was taken on the current source of that kernel."""
+    src = source_hash(files)
     out = {}
-    for path in (TRAFFIC_FILE, COUNTERS_FILE):
+    for path in paths:
         if not os.path.exists(path):
             continue
         txt = open(path).read()
-        m_src = re.search(r"march_source_sha256_16:\s*([0-9a-f]+)", txt)
+        m_src = re.search(tag + r":\s*([0-9a-f]+)", txt)
         if not m_src or m_src.group(1) != src:
             continue
         for key, val in re.findall(r"^(\w+):\s*([0-9.eE+-]+)\s*$", txt, re.M):
@@ -533,6 +542,9 @@ def adjoint_leg(args, api, I, torch, dev):
     torch.cuda.empty_cache()
     flops_eq = ADJ_FLOPS_PER_CROSSING["fp32"] + 2 * ADJ_FLOPS_PER_CROSSING["fp64"]
     achieved = flops_eq * cross / (bwd_ms * 1e-3) / 1e12
+    # the scatter's atomic bytes from the committed counter summary (same source only)
+    prof = profile_figures((ADJOINT_FILE,), ADJOINT_SOURCES, "adjoint_source_sha256_16")
+    lam = 6 * n ** 3 * 4   # dL/dLambda: six FP32 components per vertex
     return {"workload": "adjoint: L = sum(w kappa), w ~ N(0,1), 1024x1024 rays over 5x5 deg "
                         "to chi_s = 256 Mpc/h through a 256^3 FP32 Gaussian potential (box "
                         "256 Mpc/h); backward through the march, the vertex mean and the "
@@ -545,7 +557,15 @@ def adjoint_leg(args, api, I, torch, dev):
                          "flops_per_crossing": {**ADJ_FLOPS_PER_CROSSING,
                                                 "fp32_equivalent": flops_eq},
                          "kernel": "the backward call (scatter_kernel, then transpose_kernel), "
-                                   "timed with HIP events on its stream"}}
+                                   "timed with HIP events on its stream",
+                         "scatter_atomic_bytes_per_launch": prof.get(
+                             "scatter_write_bytes_per_launch"),
+                         "lambda_bytes": lam,
+                         "scatter_atomic_bytes_over_lambda": (
+                             prof["scatter_write_bytes_per_launch"] / lam
+                             if "scatter_write_bytes_per_launch" in prof else None),
+                         "scatter_valu_insts_per_wave_crossing": prof.get(
+                             "scatter_valu_insts_per_wave_crossing")}}
 
 
 def amr_profile(args, api, I, torch, dev):
