@@ -133,12 +133,13 @@ __global__ __launch_bounds__(64 * TY) void vertex_tensor_uniform_kernel(const In
   int slot = 0;
   int gz = (k0 - 2) % n;
   if (gz < 0) gz += n;
-  // this thread's part of plane p (x fastest, wrapped or zero-padded).  With
-  // FP32 records it is read one plane ahead, so that the loads of plane p + 1
-  // are in flight while plane p is differenced and its vertices stored; with
-  // FP64 records (one workgroup per CU) reading ahead is slower (3.3 against
-  // 2.2 ms for 512^3), and each plane is read when it is staged.
-  constexpr bool kAhead = sizeof(Acc) == 4;
+  // this thread's part of plane p (x fastest, wrapped or zero-padded), read
+  // one plane ahead, so that the loads of plane p + 1 are in flight while
+  // plane p is differenced and its vertices stored.  FP64 records written
+  // with three per-lane stores each (vertex boxes) read each plane when it
+  // is staged: there reading ahead was slower (3.3 against 2.2 ms for
+  // 512^3); with their rows leaving through LDS it is faster (1.76 -> 1.38).
+  constexpr bool kAhead = sizeof(Acc) == 4 || kRowStore;
   In pre[kStage];
   auto fetch = [&](int p, int gzp) {
     const bool zin = p >= 0 && p < n;
