@@ -126,6 +126,30 @@ __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot<I
     case 4: a[0] = acc[0]; a[1] = acc[1]; a[2] = acc[2]; a[3] = acc[3]; break;
     default: a[0] = acc[4]; a[1] = acc[5]; a[2] = acc[6]; a[3] = acc[7]; break;
   }
+  // the face's corners j = i_a + 2 i_b (a < b the two axes other than the
+  // face's axis k = F / 2, which sits at layer F % 2): their lattice
+  // coordinates take one of two values per axis, formed once per wavefront.
+  // Lanes 0..7 will hold the sums of corner 2 b0 + b1 (lane bits 1, 0),
+  // components 3 b2 .. 3 b2 + 2; every lane reads its slot of the cache now
+  // (lanes 8..63 a slot of the same face, unused), so that the LDS reads are
+  // in flight during the reduction.
+  const int k = F >> 1, sd = F & 1;
+  const int X1 = W0 + 1 == n ? 0 : W0 + 1, Y1 = W1 + 1 == n ? 0 : W1 + 1;
+  const int Z1 = W2 + 1 == n ? 0 : W2 + 1;
+  const int ia = (lane >> 1) & 1, ib = lane & 1;
+  const int bx = k == 0 ? sd : ia;
+  const int by = k == 1 ? sd : (k == 0 ? ia : ib);
+  const int bz = k == 2 ? sd : ib;
+  const int cx = bx ? X1 : W0, cy = by ? Y1 : W1, cz = bz ? Z1 : W2;
+  const Id my_vid = ((Id)cz * (Id)n + (Id)cy) * (Id)n + (Id)cx;
+  const int my_slot = ((W0 + bx) & 7) | (((W1 + by) & 7) << 3) | (((W2 + bz) & 3) << 6);
+  const int cb = (lane & 4) ? 3 : 0;
+  CacheSlot<Id>& e = cache[my_slot];
+  const Id tag = e.tag;
+  float held[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) held[i] = e.v[cb + i];
+  __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the reduction
   // the first halving step is taken on the products as they are formed: a
   // lane with bit 0 set keeps corners 2 and 3 and sends 0 and 1, a lane
   // with it clear the reverse (the sent products are added by the DPP move
@@ -154,30 +178,14 @@ __device__ __forceinline__ void retire_face(float* __restrict__ lam, CacheSlot<I
                                                       false, false);
     x[i] = __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
   }
-  // the face's corners j = i_a + 2 i_b (a < b the two axes other than the
-  // face's axis k = F / 2, which sits at layer F % 2): their lattice
-  // coordinates take one of two values per axis, formed once per wavefront
-  const int k = F >> 1, sd = F & 1;
-  const int X1 = W0 + 1 == n ? 0 : W0 + 1, Y1 = W1 + 1 == n ? 0 : W1 + 1;
-  const int Z1 = W2 + 1 == n ? 0 : W2 + 1;
   if (lane < 8) {
-    const int ia = (lane >> 1) & 1, ib = lane & 1;   // lane bits 1, 0: j = 2 b0 + b1
-    const int bx = k == 0 ? sd : ia;
-    const int by = k == 1 ? sd : (k == 0 ? ia : ib);
-    const int bz = k == 2 ? sd : ib;
-    const int cx = bx ? X1 : W0, cy = by ? Y1 : W1, cz = bz ? Z1 : W2;
-    const Id my_vid = ((Id)cz * (Id)n + (Id)cy) * (Id)n + (Id)cx;
-    const int my_slot = ((W0 + bx) & 7) | (((W1 + by) & 7) << 3) | (((W2 + bz) & 3) << 6);
-    const int cb = (lane & 4) ? 3 : 0;
-    CacheSlot<Id>& e = cache[my_slot];
-    const Id tag = e.tag;
     if (tag == my_vid) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) e.v[cb + i] += x[i];
+      for (int i = 0; i < 3; ++i) e.v[cb + i] = held[i] + x[i];
     } else {
       if (tag != (Id)~(Id)0) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) atomicAdd(lam + (uint64_t)tag * 6 + cb + i, e.v[cb + i]);
+        for (int i = 0; i < 3; ++i) atomicAdd(lam + (uint64_t)tag * 6 + cb + i, held[i]);
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) e.v[cb + i] = x[i];
