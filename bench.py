@@ -54,6 +54,7 @@ ADJ_FLOPS_PER_CROSSING = {"fp32": 3 * (6 + 6 + 17 + 8) + 3 + 48, "fp64": 13}
 BYTES_PER_VERTEX = {"fp32": 4 + 24, "fp64": 4 + 48}  # potential in, 6 components out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_traffic.md")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "march_uniform_lightcone_counters.md")
+WAVE_FILE = os.path.join(ROOT, "profiles", "wave_state_counters.md")
 MARCH_SOURCES = ["paper_1601_02012_amd/csrc/rr_march_uniform.hip",
                  "paper_1601_02012_amd/csrc/rr_ray.hpp",
                  "paper_1601_02012_amd/csrc/rr_internal.hpp"]
@@ -79,7 +80,7 @@ def march_source_hash():
     return source_hash(MARCH_SOURCES)
 
 
-def profile_figures(paths=(TRAFFIC_FILE, COUNTERS_FILE), files=MARCH_SOURCES,
+def profile_figures(paths=(TRAFFIC_FILE, COUNTERS_FILE, WAVE_FILE), files=MARCH_SOURCES,
                     tag="march_source_sha256_16"):
     """Figures from the committed rocprofv3 summaries (for the march: HBM bytes per
     launch, L2 hit fraction, VALU busy fraction, VALU instructions per crossing), each
@@ -831,6 +832,8 @@ def main():
                      "l2_hit_frac": prof.get("march_l2_hit_frac"),
                      "valu_busy_frac": prof.get("march_valu_busy_frac"),
                      "valu_insts_per_crossing": prof.get("march_valu_insts_per_crossing"),
+                     "hw_fp32_flops_per_crossing": prof.get("march_hw_fp32_flops_per_crossing"),
+                     "lane_utilisation": prof.get("march_lane_utilisation"),
                      "kernel": "march_uniform (FP32-Kahan)",
                      "bytes_per_crossing": BYTES_PER_CROSSING["fp32"],
                      "launch_ms": march_launch_ms, "crossings_per_launch": cross_per_launch,
