@@ -63,6 +63,8 @@ def test_committed_summaries_carry_the_lines_bench_reads():
              ("hbm_bytes_per_launch", "tensor_hbm_bytes_per_build")),
             (b.COUNTERS_FILE, "march_source_sha256_16",
              ("march_valu_insts_per_crossing", "march_l2_hit_frac", "march_valu_busy_frac")),
+            (b.WAVE_FILE, "march_source_sha256_16",
+             ("march_hw_fp32_flops_per_crossing", "march_lane_utilisation")),
             (b.ADJOINT_FILE, "adjoint_source_sha256_16",
              ("scatter_write_bytes_per_launch", "scatter_valu_insts_per_wave_crossing"))):
         txt = open(path).read()
