@@ -1,4 +1,9 @@
-"""Full-size AMR and batched cases, checked on sampled rays and leaves.
+"""Full-size cases, checked on every ray or on sampled rays and leaves.
+
+The light cone is the 512^3 lognormal potential of a 1 Gpc/h box over 20
+segments to z = 1 with 2048^2 rays: Method B on every ray, the many-source,
+Method A and ISW legs on a 1/64 subset of the map's tiles, each traced on the
+GPU over the whole map in the launch configuration that is timed.
 
 The AMR octree is the 256^3-base, 4-level tree refined where a cell holds more
 than 8 of 2^24 particles (NFW haloes on a lognormal background).  The GPU
@@ -185,12 +190,22 @@ def test_batched_bundles_persistent_and_graph(api, oracle, amr, amr_corners):
     plan.close()
 
 
+# the many-source leg's source redshifts
+LIGHTCONE_SOURCE_Z = [1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1]
+
+
 @pytest.fixture(scope="module")
-def lightcone():
+def lightcone_fields():
+    """(delta0, phi0) of the 512^3, 1 Gpc/h light cone (FP64)."""
+    return I.config2_fields(512, 1000.0)
+
+
+@pytest.fixture(scope="module")
+def lightcone(lightcone_fields):
     """The light cone to z = 1: 512^3 lognormal potential in a 1 Gpc/h box,
     scaled by s_k for each of the 20 segments, 2048^2 rays over 5x5 deg."""
     n, box, nray = 512, 1000.0, 2048
-    _, phi0 = I.config2_fields(n, box)
+    phi0 = lightcone_fields[1]
     fov = math.radians(5.0)
     dirs = I.fov_directions((0.0, 0.0, 1.0), fov, fov, nray, nray)
     return n, box, nray, phi0, I.lightcone_segments(20), I.chi_of_z(1.0), dirs
@@ -204,7 +219,15 @@ def test_lightcone_full_size_every_ray(api, oracle, lightcone):
     the crossing hashes and counts of all 4 194 304 rays equal the oracle's
     bit for bit (the rays traced again with crossing hashes), every ray
     finishes, and the final kappa of every ray is within
-    max(1e-5 |kappa|, 1e-7)."""
+    max(1e-5 |kappa|, 1e-7).
+
+    The same tensors also carry the many-source leg as it is timed: ten
+    sources (z = 1.0, 0.9, ..., 0.1) in one walk over the 20 segments with
+    FP32-Kahan moments, then kappa from the pieces.  On a 1/64 subset of the
+    map's 8x8 tiles the walk's crossing hashes and counts of every segment
+    equal the oracle's (its walk carrying moments and pieces over the
+    segments the same way) and every source's kappa is within
+    max(1e-5 |kappa|, 1e-7) of the oracle's."""
     import torch
     n, box, nray, phi0, segs, chi_s, dirs = lightcone
     obs = (0.0, 0.0, 0.0)
@@ -221,6 +244,13 @@ def test_lightcone_full_size_every_ray(api, oracle, lightcone):
     t = None
     ref = np.zeros(nr)
     total = 0
+    ids = tile_subset(nray, nray)
+    sub = np.ascontiguousarray(dirs[ids])
+    src = np.array([I.chi_of_z(z) for z in LIGHTCONE_SOURCE_Z])
+    state = api.SourcesOutput(torch.zeros((nr, 4), dtype=torch.float32, device="cuda"),
+                              torch.zeros((nr, src.size, 2), dtype=torch.float64, device="cuda"),
+                              torch.zeros(nr, dtype=torch.int32, device="cuda"))
+    dstate = mom = pcs = None
     for k, (hi, lo, s) in enumerate(segs):
         phi = (phi0_d * s).to(torch.float32).contiguous()
         g = api.Grid(phi, box)
@@ -235,19 +265,147 @@ def test_lightcone_full_size_every_ray(api, oracle, lightcone):
         c_gpu = dbg.count.cpu().numpy()
         tv = oracle.vertex_tensor(phi.double().cpu().numpy())
         r = oracle.trace_uniform(n, box, obs, dirs, chi_s, hi, lo, tv=tv)
-        del tv
         assert np.all(r.status == oracle.RAY_OK), k
         assert np.array_equal(c_gpu, r.ncross), k
         assert np.array_equal(h_gpu, r.hash), k
         ref += r.kappa
         total += int(r.ncross.sum())
+        # the many-source walk through the same tensor
+        api.trace_sources(plan, t, bundle, obs, src, state=state, persistent=0)
+        dstate = api.trace_sources(plan, t, bundle, obs, src, state=dstate, debug=True,
+                                   persistent=0)
+        rs = oracle.trace_uniform_sources(n, box, obs, sub, hi, lo, src, tv=tv, moments=mom,
+                                          pieces=pcs)
+        del tv
+        mom, pcs = rs.moments, rs.pieces
+        assert np.all(rs.status == oracle.RAY_OK), k
+        assert np.array_equal(dstate.count.cpu().numpy()[ids], rs.ncross), k
+        assert np.array_equal(hashes_u64(dstate.hash)[ids], rs.hash), k
         print(f"[lightcone] segment {k}: {int(r.ncross.sum())} crossings, every ray's hash and "
-              "count equal", flush=True)
+              "count equal; the sampled rays' many-source walk too", flush=True)
     torch.cuda.synchronize()
     assert bool((st == 0).all())
     ok, worst = kappa_tolerance_ok(kap.double().cpu().numpy(), ref)
     print(f"[lightcone] {total} crossings; worst |err| / tol over {nr} rays: {worst:.3g}",
           flush=True)
+    assert ok, worst
+    assert bool((state.status == 0).all())
+    kw = api.kappa_from_pieces(plan, t, src, state).cpu().numpy()[ids]
+    kr = oracle.kappa_from_pieces(src, box, n, mom, pcs)
+    worst = 0.0
+    for j in range(src.size):
+        ok, w = kappa_tolerance_ok(kw[:, j], kr[:, j])
+        worst = max(worst, w)
+        assert ok, (LIGHTCONE_SOURCE_Z[j], w)
+    print(f"[lightcone] many sources: {ids.size} sampled rays x {src.size} sources; worst "
+          f"|err| / tol {worst:.3g}", flush=True)
+    t.close()
+    plan.close()
+
+
+def _lightcone_gpu(api, lightcone):
+    import torch
+    n, box, nray, phi0, segs, chi_s, dirs = lightcone
+    nr = nray * nray
+    dirs_d = torch.as_tensor(dirs, device="cuda")
+    zeros = lambda dt: torch.zeros(nr, dtype=dt, device="cuda")
+    return dirs_d, zeros, tile_subset(nray, nray)
+
+
+def test_lightcone_method_a_full_size_tile_subset(api, oracle, lightcone, lightcone_fields):
+    """Method A over the light cone as it is timed: per segment the vertex
+    fields (c s_k delta, grad Phi_k) of the whole 512^3 grid rebuilt, all
+    2048^2 rays in one one-wavefront-per-tile launch, kappa and its
+    compensation carried over the 20 segments in FP32-Kahan.  On a 1/64
+    subset of the map's 8x8 tiles the crossing hashes and counts of every
+    segment equal the FP64 oracle's bit for bit and the final kappa is within
+    max(1e-5 |kappa|, 1e-7)."""
+    import torch
+    n, box, nray, phi0, segs, chi_s, dirs = lightcone
+    obs = (0.0, 0.0, 0.0)
+    dirs_d, zeros, ids = _lightcone_gpu(api, lightcone)
+    sub = np.ascontiguousarray(dirs[ids])
+    d32 = lightcone_fields[0].astype(np.float32)
+    d64 = d32.astype(np.float64)
+    gd = api.Grid(torch.as_tensor(d32, device="cuda"), box, field="delta")
+    t = api.TidalTensor(gd, "fp32")
+    plan = api.Plan()
+    kap, comp, st = zeros(torch.float32), zeros(torch.float32), zeros(torch.int32)
+    c0 = I.poisson_coefficient()
+    ref = np.zeros(ids.size)
+    for k, (hi, lo, s) in enumerate(segs):
+        phi = (phi0 * s).astype(np.float32)
+        gp = api.Grid(torch.as_tensor(phi, device="cuda"), box)
+        t.build_method_a(gd, gp, c0 * s)
+        bundle = [api.RayBundle(dirs_d, nray, nray, chi_s, hi, lo)]
+        api.trace(plan, t, bundle, obs, kappa=kap, kappa_comp=comp, status=st, persistent=0)
+        dbg = api.trace(plan, t, bundle, obs, debug=True, persistent=0)
+        r = oracle.trace_uniform_method_a(n, box, obs, sub, chi_s, hi, lo, delta_coeff=c0 * s,
+                                          phi=phi.astype(np.float64), delta=d64)
+        assert np.all(r.status == oracle.RAY_OK), k
+        assert np.array_equal(dbg.count.cpu().numpy()[ids], r.ncross), k
+        assert np.array_equal(hashes_u64(dbg.hash)[ids], r.hash), k
+        ref += r.kappa
+        del dbg, gp
+    torch.cuda.synchronize()
+    assert bool((st == 0).all())
+    ok, worst = kappa_tolerance_ok(kap.double().cpu().numpy()[ids], ref)
+    print(f"[method A] {ids.size} sampled rays: hashes and counts equal in all 20 segments; "
+          f"worst |err| / tol {worst:.3g}", flush=True)
+    assert ok, worst
+    t.close()
+    plan.close()
+
+
+def test_lightcone_isw_full_size_tile_subset(api, oracle, lightcone):
+    """The ISW leg as it is timed: per segment the vertex field of
+    (Phi_k - Phi_k-1)/dt over the whole grid and all 2048^2 rays with the
+    constant kernel 2 a_k / c, FP32-Kahan over the 20 segments.  On a 1/64
+    tile subset the crossing hashes and counts of every segment equal the
+    oracle's and the final map is within max(1e-5 |x|, 1e-5 rms): the map's
+    rms is ~2e-6, so the kappa floor of 1e-7 (1e-5 of a kappa map's rms)
+    becomes 1e-5 of this map's rms."""
+    import torch
+    n, box, nray, phi0, segs, chi_s, dirs = lightcone
+    obs = (0.0, 0.0, 0.0)
+    dirs_d, zeros, ids = _lightcone_gpu(api, lightcone)
+    sub = np.ascontiguousarray(dirs[ids])
+    steps = I.isw_steps(len(segs))
+    plan = api.Plan()
+    out, comp, st = zeros(torch.float32), zeros(torch.float32), zeros(torch.int32)
+    ref = np.zeros(ids.size)
+    # the potential one step before the first segment
+    prev = (phi0 * segs[0][2]).astype(np.float32) * np.float32(steps[0][0] / steps[0][1])
+    gprev = api.Grid(torch.as_tensor(prev, device="cuda"), box)
+    t = None
+    for k, (hi, lo, s) in enumerate(segs):
+        curr = (phi0 * s).astype(np.float32)
+        gcurr = api.Grid(torch.as_tensor(curr, device="cuda"), box)
+        if t is None:
+            t = api.TidalTensor(api.Grid(gcurr.values, box, field="phi_dot"), "fp32")
+        t.build_isw(gcurr, gprev, steps[k][2])
+        bundle = [api.RayBundle(dirs_d, nray, nray, chi_s, hi, lo)]
+        api.trace(plan, t, bundle, obs, kappa=out, kappa_comp=comp, status=st,
+                  quantity="scalar", kappa_scale=steps[k][3], persistent=0)
+        dbg = api.trace(plan, t, bundle, obs, quantity="scalar", kappa_scale=steps[k][3],
+                        debug=True, persistent=0)
+        qv = oracle.isw_vertex_field(curr.astype(np.float64), prev.astype(np.float64),
+                                     steps[k][2])
+        r = oracle.trace_uniform_isw(n, box, obs, sub, hi, lo, qv=qv, scale=steps[k][3])
+        del qv
+        assert np.all(r.status == oracle.RAY_OK), k
+        assert np.array_equal(dbg.count.cpu().numpy()[ids], r.ncross), k
+        assert np.array_equal(hashes_u64(dbg.hash)[ids], r.hash), k
+        ref += r.kappa
+        prev, gprev = curr, gcurr
+        del dbg
+    torch.cuda.synchronize()
+    assert bool((st == 0).all())
+    rms = float(np.sqrt(np.mean(ref ** 2)))
+    assert 1e-7 < rms < 1e-4, rms
+    ok, worst = kappa_tolerance_ok(out.double().cpu().numpy()[ids], ref, abs_=1e-5 * rms)
+    print(f"[isw] {ids.size} sampled rays, map rms {rms:.3g}: hashes and counts equal in all "
+          f"20 segments; worst |err| / tol {worst:.3g}", flush=True)
     assert ok, worst
     t.close()
     plan.close()
