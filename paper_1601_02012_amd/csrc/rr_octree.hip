@@ -400,7 +400,7 @@ constexpr int kOctTidal = 0, kOctNgp = 1, kOctSources = 3;
 // with its child link; level changes and edge crossings reload all eight.
 // A crossing that stays on level 0 or inside the parent oct needs no walk
 // from the base cell.
-template <typename R, bool kDebug, int kMode, typename Off>
+template <typename R, bool kDebug, int kMode, typename Off, bool kOverlap>
 __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceArgs& a,
                           const DevBundle& B, int64_t ray) {
   const int64_t out = B.ray_offset + ray;
@@ -525,6 +525,59 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   const int64_t maxc = a.max_crossings > 0 ? a.max_crossings : INT64_MAX;
   bool paused = false;
 
+  // the integral of the piece [chi_a, chiB] of the current leaf (corners q,
+  // entry coordinates fA, exit coordinates fB), its accumulation and, in the
+  // many-source walk, the hand-out at a source distance
+  auto piece = [&](double chi_a, double chiB, const R* fB, R L) {
+    R ic, ic2 = 0;
+    if constexpr (kMode == kOctNgp) {
+      // Eq. (Iclensing_ngp): the leaf's centre value times the integral of g,
+      // L (g(mid) - L^2 / (12 chi_s)) with g(chi) = chi (chi_s - chi) / chi_s
+      const R* tc = cv + 6 * (uint64_t)cell;
+      R Qc = P[0] * tc[0];
+#pragma unroll
+      for (int c = 1; c < 6; ++c) Qc = fma(P[c], tc[c], Qc);
+      const double mid = chiB + 0.5 * (chi_a - chiB);
+      const R gm = (R)mid * (R)(B.chi_s - mid) - L * L * (R)(1.0 / 12.0);
+      ic = Qc * (gm * L * inv_chis) * scale;
+    } else if constexpr (kMode == kOctSources) {
+      R ma, mb;
+      cell_moments<R>(q, fA, fB, L, (R)chiB, ma, mb);
+      ic = ma * scale;
+      ic2 = mb * scale;
+    } else {
+      ic = cell_integral<R>(q, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+    }
+    if constexpr (sizeof(R) == 4) {
+      kahan_add(sum, comp, ic);
+      if constexpr (kMode == kOctSources) kahan_add(sum2, comp2, ic2);
+    } else {
+      sum += ic;
+      if constexpr (kMode == kOctSources) sum2 += ic2;
+    }
+    if constexpr (kDebug) {
+      if (a.hash) hv = fnv_piece(hv, (int64_t)cell, chi_a, chiB);
+      if (a.log && count < a.log_stride) {
+        LogRecord* L0 = reinterpret_cast<LogRecord*>(a.log) + out * a.log_stride + count;
+        L0->cell = (int64_t)cell;
+        L0->chi_a = chi_a;
+        L0->chi_b = chiB;
+      }
+    }
+    ++count;
+    if constexpr (kMode == kOctSources) {
+      if (src_j == chiB) {
+        // hand out the two integrals accumulated since the previous stop
+        double* pc = a.pieces + (out * a.n_src + jn) * 2;
+        pc[0] = (double)sum - (double)comp;
+        pc[1] = (double)sum2 - (double)comp2;
+        sum = 0; comp = 0.0f; sum2 = 0; comp2 = 0.0f;
+        ++jn;
+        src_j = jn < a.n_src ? a.src[jn] : -1.0;
+      }
+    }
+  };
+
   for (;;) {
     if (chiA <= a.pause_chi) {   // the rest of the window is a later pass's
       paused = true;
@@ -544,66 +597,23 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     for (int k = 0; k < 3; ++k) stepped[k] = te[k] == chiB;
 
     const R L = (R)(chiA - chiB);
-    R ic, ic2 = 0;
     R fB[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) fB[k] = (R)1 - absd[k] * (R)(chiB - te[k]);
-    if constexpr (kMode == kOctNgp) {
-      // Eq. (Iclensing_ngp): the leaf's centre value times the integral of g,
-      // L (g(mid) - L^2 / (12 chi_s)) with g(chi) = chi (chi_s - chi) / chi_s
-      const R* tc = cv + 6 * (uint64_t)cell;
-      R Qc = P[0] * tc[0];
+    const double chi_a = chiA;
+    bool stop = chiB == lo;
+    if constexpr (kMode == kOctSources) stop = stop || !(stepped[0] || stepped[1] || stepped[2]);
+    if (stop) {
+      piece(chi_a, chiB, fB, L);
+      if (chiB == lo) break;
+      // stopped at a source distance inside the leaf: same corners
+      chiA = chiB;
 #pragma unroll
-      for (int c = 1; c < 6; ++c) Qc = fma(P[c], tc[c], Qc);
-      const double mid = chiB + 0.5 * (chiA - chiB);
-      const R gm = (R)mid * (R)(B.chi_s - mid) - L * L * (R)(1.0 / 12.0);
-      ic = Qc * (gm * L * inv_chis) * scale;
-    } else if constexpr (kMode == kOctSources) {
-      R ma, mb;
-      cell_moments<R>(q, fA, fB, L, (R)chiB, ma, mb);
-      ic = ma * scale;
-      ic2 = mb * scale;
-    } else {
-      ic = cell_integral<R>(q, fA, fB, L, (R)chiB, (R)(B.chi_s - chiB), inv_chis) * scale;
+      for (int k = 0; k < 3; ++k) fA[k] = fB[k];
+      continue;
     }
-    if constexpr (sizeof(R) == 4) {
-      kahan_add(sum, comp, ic);
-      if constexpr (kMode == kOctSources) kahan_add(sum2, comp2, ic2);
-    } else {
-      sum += ic;
-      if constexpr (kMode == kOctSources) sum2 += ic2;
-    }
-    if constexpr (kDebug) {
-      if (a.hash) hv = fnv_piece(hv, (int64_t)cell, chiA, chiB);
-      if (a.log && count < a.log_stride) {
-        LogRecord* L0 = reinterpret_cast<LogRecord*>(a.log) + out * a.log_stride + count;
-        L0->cell = (int64_t)cell;
-        L0->chi_a = chiA;
-        L0->chi_b = chiB;
-      }
-    }
-    ++count;
-    if constexpr (kMode == kOctSources) {
-      if (src_j == chiB) {
-        // hand out the two integrals accumulated since the previous stop
-        double* pc = a.pieces + (out * a.n_src + jn) * 2;
-        pc[0] = (double)sum - (double)comp;
-        pc[1] = (double)sum2 - (double)comp2;
-        sum = 0; comp = 0.0f; sum2 = 0; comp2 = 0.0f;
-        ++jn;
-        src_j = jn < a.n_src ? a.src[jn] : -1.0;
-      }
-    }
-    if (chiB == lo) break;
+    if constexpr (!kOverlap) piece(chi_a, chiB, fB, L);
     chiA = chiB;
-    if constexpr (kMode == kOctSources) {
-      if (!(stepped[0] || stepped[1] || stepped[2])) {
-        // stopped at a source distance inside the leaf: same corners
-#pragma unroll
-        for (int k = 0; k < 3; ++k) fA[k] = fB[k];
-        continue;
-      }
-    }
 
     // step the crossed axes on level l; track the base cell
     const int ch_old = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
@@ -637,23 +647,40 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     }
     // the target: a same-level leaf across one face keeps four corner values
     // and loads the other four together with its child link; a refined target
-    // (the loads are dropped), a coarser one or an edge crossing reloads all
+    // (the loads are dropped), a coarser one or an edge crossing reloads all.
+    // With kOverlap the four loads are issued for every target (each cell,
+    // leaf or not, has its block, so they stay in bounds where they are not
+    // used) and the integral of the leaf being left is computed while they
+    // are in flight; otherwise the integral comes first and the loads only
+    // for a same-level face crossing (the register budget of the persistent
+    // march cannot hold the loads in flight across the integral).
     const int l_in = l;
     const bool single = (int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1;
     bool inner[3] = {false, false, false};   // a crossed plane inside the new (coarser) leaf
     int kc = T.child[nc];
     bool kept = false;
+    const bool k0 = stepped[0], k1 = stepped[1];
+    const bool same = kMode != kOctNgp && lev == l && single;
+    R F0 = 0, F1 = 0, F2 = 0, F3 = 0;
+    if (kOverlap ? kMode != kOctNgp : same) {
+      // slots of the new exit face: (1 << k) | i_a << a | i_b << b, a < b the other axes
+      const int sk = k0 ? 1 : (k1 ? 2 : 4);
+      const int sa = k0 ? 2 : 1;
+      const int sb = k0 || k1 ? 4 : 2;
+      F0 = leaf_corner<R, Off>(cv, nc, sk ^ flip, P);
+      F1 = leaf_corner<R, Off>(cv, nc, (sk | sa) ^ flip, P);
+      F2 = leaf_corner<R, Off>(cv, nc, (sk | sb) ^ flip, P);
+      F3 = leaf_corner<R, Off>(cv, nc, (sk | sa | sb) ^ flip, P);
+    }
+    if constexpr (kOverlap) {
+      piece(chi_a, chiB, fB, L);
+      // the integral is computed here, between the issue of the loads and
+      // the first use of their values: neither moves past these statements
+      asm volatile("" ::"v"(sum), "v"(comp));
+      asm volatile("" ::"v"(F0), "v"(F1), "v"(F2), "v"(F3));
+    }
     if constexpr (kMode != kOctNgp) {
-      if (lev == l && single) {
-        const bool k0 = stepped[0], k1 = stepped[1];
-        // slots of the new exit face: (1 << k) | i_a << a | i_b << b, a < b the other axes
-        const int sk = k0 ? 1 : (k1 ? 2 : 4);
-        const int sa = k0 ? 2 : 1;
-        const int sb = k0 || k1 ? 4 : 2;
-        const R F0 = leaf_corner<R, Off>(cv, nc, sk ^ flip, P);
-        const R F1 = leaf_corner<R, Off>(cv, nc, (sk | sa) ^ flip, P);
-        const R F2 = leaf_corner<R, Off>(cv, nc, (sk | sb) ^ flip, P);
-        const R F3 = leaf_corner<R, Off>(cv, nc, (sk | sa | sb) ^ flip, P);
+      if (same) {
         if (__ballot(kc < 0 && !k0 && !k1) == __ballot(1)) {
           // every marching lane crossed a z face into a leaf of its level
           // (lines of sight near the z axis): no selects
@@ -759,7 +786,7 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
   }
 }
 
-template <typename R, bool kDebug, int kMode, typename Off>
+template <typename R, bool kDebug, int kMode, typename Off, bool kOverlap>
 __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const TraceArgs& a,
                                          int64_t tile, int lane) {
   const int b = find_bundle(a.bundles, a.n_bundles, tile);
@@ -767,7 +794,7 @@ __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const Trace
   int tx, ty;
   zorder_tile(tile - B.tile_begin, B.tiles_x, B.tiles_y, tx, ty);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kMode, Off>(T, cv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kMode, Off, kOverlap>(T, cv, a, B, (int64_t)iy * B.nx + ix);
 }
 
 template <typename R, bool kDebug, int kMode, typename Off>
@@ -780,7 +807,7 @@ __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __re
   const int64_t tile =
       ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
-  oct_tile<R, kDebug, kMode, Off>(T, cv, a, tile, lane);
+  oct_tile<R, kDebug, kMode, Off, kMode == kOctTidal>(T, cv, a, tile, lane);
 }
 
 // The FP32 tidal march (no debug outputs, 32-bit offsets) fits 128 VGPRs
@@ -796,7 +823,7 @@ void march_octree_persistent(Tree T, const R* __restrict__ cv, TraceArgs a) {
   for (;;) {
     const int64_t tile = next_tile(a.queue, a.n_tiles, q, tried, lane);
     if (tile < 0) break;
-    oct_tile<R, kDebug, kMode, Off>(T, cv, a, tile, lane);
+    oct_tile<R, kDebug, kMode, Off, false>(T, cv, a, tile, lane);
   }
 }
 
