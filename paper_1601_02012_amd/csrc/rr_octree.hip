@@ -399,7 +399,8 @@ constexpr int kOctTidal = 0, kOctNgp = 1, kOctSources = 3;
 // the vertex alone) and loads the new leaf's four exit-face corners together
 // with its child link; level changes and edge crossings reload all eight.
 // A crossing that stays on level 0 or inside the parent oct needs no walk
-// from the base cell.
+// from the base cell.  kOverlap: the next leaf's loads are issued before the
+// integral of the leaf being left (see the target step below).
 template <typename R, bool kDebug, int kMode, typename Off, bool kOverlap>
 __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceArgs& a,
                           const DevBundle& B, int64_t ray) {
@@ -794,7 +795,8 @@ __device__ __forceinline__ void oct_tile(const Tree& T, const R* cv, const Trace
   int tx, ty;
   zorder_tile(tile - B.tile_begin, B.tiles_x, B.tiles_y, tx, ty);
   const int ix = tx * 8 + (lane & 7), iy = ty * 8 + (lane >> 3);
-  if (ix < B.nx && iy < B.ny) trace_oct<R, kDebug, kMode, Off, kOverlap>(T, cv, a, B, (int64_t)iy * B.nx + ix);
+  if (ix < B.nx && iy < B.ny)
+    trace_oct<R, kDebug, kMode, Off, kOverlap>(T, cv, a, B, (int64_t)iy * B.nx + ix);
 }
 
 template <typename R, bool kDebug, int kMode, typename Off>
@@ -807,13 +809,17 @@ __global__ __launch_bounds__(256) void march_octree_kernel(Tree T, const R* __re
   const int64_t tile =
       ((blk % 8) * per + blk / 8) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(wave);
   if (tile >= a.n_tiles) return;
+  // the tidal march computes each integral while the next leaf's corner
+  // loads are in flight (the register budget of a direct launch holds them)
   oct_tile<R, kDebug, kMode, Off, kMode == kOctTidal>(T, cv, a, tile, lane);
 }
 
 // The FP32 tidal march (no debug outputs, 32-bit offsets) fits 128 VGPRs
 // without spilling: four waves per SIMD keep a 16-wave-per-CU persistent grid
 // resident at once (at 132 VGPRs only three were; the 64 batched bundles
-// 2.34 -> 2.02 s).  The other instantiations spill under that cap.
+// 2.34 -> 2.02 s).  The other instantiations spill under that cap.  Under
+// it the loads of the next leaf cannot stay in flight across an integral
+// (the compiler then serialises them), so the integral comes first.
 template <typename R, bool kDebug, int kMode, typename Off>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     sizeof(R) == 4 && kMode == 0 && !kDebug && sizeof(Off) == 4 ? 4 : 1)))
