@@ -617,34 +617,52 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     chiA = chiB;
 
     // step the crossed axes on level l; track the base cell
-    const int ch_old = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
-    bool sib = l > 0;
-    bool moved = false;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (stepped[k]) {
-        const int mo = m[k];
-        const int s = r[k] > 0.0 ? -1 : 1;
-        m[k] = mo + s;
-        sib = sib && ((m[k] >> 1) == (mo >> 1));
-        if ((m[k] >> l) != (mo >> l)) {
-          const int w = wb[k] + s;
-          wb[k] = w < 0 ? n - 1 : (w == n ? 0 : w);
-          moved = true;
-        }
-      }
-    }
-    if (moved) blin = ((Off)wb[2] * (Off)n + (Off)wb[1]) * (Off)n + (Off)wb[0];
-    // the level-l cell past the face: a base cell, a sibling, or a walk
+    const bool single = (int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1;
     Off nc;
     int lev = l;
-    if (l == 0) {
+    if (__ballot(l == 0 && single) == __ballot(1)) {
+      // every lane is on level 0 and crosses one face: the new base cell
+      // without branches (its index moves by the wrapped step times the
+      // axis stride)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int st = stepped[k] ? (r[k] > 0.0 ? -1 : 1) : 0;
+        m[k] += st;
+        int w = wb[k] + st;
+        w = w < 0 ? n - 1 : (w == n ? 0 : w);
+        const int64_t stride = k == 0 ? 1 : (k == 1 ? (int64_t)n : (int64_t)n * n);
+        blin += (Off)((int64_t)(w - wb[k]) * stride);
+        wb[k] = w;
+      }
       nc = blin;
-    } else if (sib) {
-      const int ch = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
-      nc = cell + (Off)(ch - ch_old);
     } else {
-      lev = descend_from<Off>(T, blin, l, m, nc);
+      const int ch_old = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
+      bool sib = l > 0;
+      bool moved = false;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (stepped[k]) {
+          const int mo = m[k];
+          const int s = r[k] > 0.0 ? -1 : 1;
+          m[k] = mo + s;
+          sib = sib && ((m[k] >> 1) == (mo >> 1));
+          if ((m[k] >> l) != (mo >> l)) {
+            const int w = wb[k] + s;
+            wb[k] = w < 0 ? n - 1 : (w == n ? 0 : w);
+            moved = true;
+          }
+        }
+      }
+      if (moved) blin = ((Off)wb[2] * (Off)n + (Off)wb[1]) * (Off)n + (Off)wb[0];
+      // the level-l cell past the face: a base cell, a sibling, or a walk
+      if (l == 0) {
+        nc = blin;
+      } else if (sib) {
+        const int ch = (m[0] & 1) | ((m[1] & 1) << 1) | ((m[2] & 1) << 2);
+        nc = cell + (Off)(ch - ch_old);
+      } else {
+        lev = descend_from<Off>(T, blin, l, m, nc);
+      }
     }
     // the target: a same-level leaf across one face keeps four corner values
     // and loads the other four together with its child link; a refined target
@@ -656,7 +674,6 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
     // for a same-level face crossing (the register budget of the persistent
     // march cannot hold the loads in flight across the integral).
     const int l_in = l;
-    const bool single = (int)stepped[0] + (int)stepped[1] + (int)stepped[2] == 1;
     bool inner[3] = {false, false, false};   // a crossed plane inside the new (coarser) leaf
     int kc = T.child[nc];
     bool kept = false;
