@@ -79,6 +79,23 @@ def test_octree_corner_tensor_matches_oracle(api, oracle, tree_case, prec, tol):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_octree_blocks_of_refined_cells_are_nan(api, tree_case, prec):
+    """Every component of the corner block of a cell that is not a leaf is
+    NaN and every leaf's block is finite: after a same-level face crossing
+    the direct march reads the target's child link only when the target's
+    corner value is NaN (a finite value shows a leaf)."""
+    t, box, phi = tree_case
+    dt = np.float64 if prec == "fp64" else np.float32
+    tt = api.TidalTensor(_gpu_octree_grid(api, t, phi, box, dt), prec).build()
+    got = tt.to_torch().double().cpu().numpy().reshape(t.n_cells, 8, 6)
+    refined = t.child_oct >= 0
+    assert refined.sum() > 0
+    assert np.all(np.isnan(got[refined]))
+    assert np.all(np.isfinite(got[~refined]))
+    tt.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_octree_trace_matches_oracle(api, oracle, plan, tree_case, prec):
     import torch
     t, box, phi = tree_case
