@@ -702,9 +702,10 @@ __device__ void trace_oct(const Tree& T, const R* __restrict__ cv, const TraceAr
       // hold NaN (corner_kernel), so a finite corner value of a same-level
       // target shows a leaf and the link is read only where that does not
       // settle it (a NaN value, a level change or an edge crossing).  The
-      // persistent march reads it ahead of its corner loads instead: there
-      // the corner values are waited for at once, and a link read after them
-      // would wait twice (batched bundles 1.90 -> 2.36 s).
+      // persistent march reads it for every target, ahead of its corner
+      // loads: reading it only where needed made that march slower (batched
+      // bundles 1.90 -> 2.36-2.38 s, with the other targets' links read
+      // before or after the corner loads).
       if (!(same && F0 == F0)) kc = T.child[nc];
     }
     if constexpr (kMode != kOctNgp) {
